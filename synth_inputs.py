@@ -1,0 +1,57 @@
+"""Seeded synthetic inputs shared by the tests, the oracle checks and bench.py.
+
+This module draws random numbers and names workloads; it holds none of the
+split-CTMRG arithmetic.  The raw PEPS tensor is returned un-symmetrised: the
+D4 projection is a step of the method, done separately by each side.
+
+Workloads (beta, D, chi, iterations / tolerance) follow the benchmark settings
+of the paper's Ising study (T = 4.4 is beta ~ 0.227; D up to 6; chi ~ D^2 and
+chi = 60..144): the paper's optimised tensors are not available, so seeded
+N(0,1) tensors of the same shape stand in for them.
+"""
+import numpy as np
+
+PHYS = 2
+
+# name -> (beta, D, chi, max_iter, tol, precision)
+WORKLOADS = {
+    "d2_chi16": dict(beta=0.20, D=2, chi=16, max_iter=40, tol=0.0, prec="fp64", seed=0),
+    "d4_chi64": dict(beta=0.2216, D=4, chi=64, max_iter=200, tol=1e-9, prec="fp32", seed=0),
+    "d5_chi100": dict(beta=0.22, D=5, chi=100, max_iter=200, tol=1e-9, prec="fp64", seed=0,
+                      fp32_params=True),
+    "d6_chi144": dict(beta=0.22, D=6, chi=144, max_iter=200, tol=1e-9, prec="bf16", seed=0),
+}
+
+
+def raw_peps(D, seed, fp32_params=False):
+    """A[p, l, u, r, d] ~ N(0, 1), float64, from numpy's default_rng(seed)."""
+    A = np.random.default_rng(seed).standard_normal((PHYS, D, D, D, D))
+    if fp32_params:
+        A = A.astype(np.float32).astype(np.float64)
+    return A
+
+
+def workload_peps(name):
+    w = WORKLOADS[name]
+    return raw_peps(w["D"], w["seed"], w.get("fp32_params", False))
+
+
+def random_directions(shape, n, seed):
+    """n raw N(0,1) directions (un-symmetrised) for finite-difference checks."""
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal(shape) for _ in range(n)]
+
+
+def serving_trace(n_requests=256, mean_rate=20.0, seed=1):
+    """Poisson arrivals and request parameters for the serving mix:
+    beta ~ U[0.18, 0.26], D in {2,3,4,5}, chi in {16,32,64,100,128}."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / mean_rate, size=n_requests)
+    t = np.cumsum(gaps)
+    reqs = []
+    for i in range(n_requests):
+        reqs.append(dict(t_arrival=float(t[i]), beta=float(rng.uniform(0.18, 0.26)),
+                         D=int(rng.choice([2, 3, 4, 5])),
+                         chi=int(rng.choice([16, 32, 64, 100, 128])),
+                         seed=1000 + i))
+    return reqs

@@ -1,0 +1,220 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the oracle.
+
+Each test names the fact it checks.  Together they are chosen so that a
+plausible slip in the oracle (a dropped factor in O, a wrong D4 permutation, a
+transposed edge tensor, a mis-wired projector, a wrong gradient normalisation)
+fails at least one of them.
+"""
+import itertools
+import warnings
+
+import numpy as np
+import pytest
+
+from oracle import exact, model, split, unsplit
+from synth_inputs import raw_peps, random_directions
+
+warnings.simplefilter("ignore")
+
+
+# ---------------------------------------------------------------- model pieces
+
+@pytest.mark.parametrize("beta", [0.05, 0.2, 0.7])
+def test_sqrtW_squares_to_W(beta):
+    s = model.sqrt_W(beta)
+    assert np.allclose(s @ s, model.boltzmann_W(beta), rtol=1e-14, atol=0)
+    # eigenvalues 2cosh(b), 2sinh(b) with eigenvectors (1,1), (1,-1)
+    assert np.isclose(s.sum(axis=1)[0] ** 2, 2 * np.cosh(beta), rtol=1e-14)
+
+
+@pytest.mark.parametrize("beta", [0.1, 0.22, 0.4])
+def test_pepo_single_site_torus(beta):
+    """A 1x1x1 periodic cube: the six legs of one O traced pairwise give
+    Z = sum_s W[s,s]^3 = 2 e^{3 beta}."""
+    O = model.pepo_O(beta)
+    Z = np.einsum("ppllkk->", O.transpose(0, 1, 2, 4, 3, 5))
+    assert np.isclose(Z, 2 * np.exp(3 * beta), rtol=1e-13)
+
+
+def test_pepo_fully_symmetric():
+    """O_h symmetry of the PEPO (Sec. IV): invariant under any leg permutation."""
+    O = model.pepo_O(0.3)
+    for perm in [(1, 0, 2, 3, 4, 5), (0, 1, 3, 2, 4, 5), (5, 4, 3, 2, 1, 0), (2, 3, 4, 5, 0, 1)]:
+        assert np.allclose(O.transpose(perm), O, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("beta", [0.1, 0.25])
+def test_pepo_two_site_torus(beta):
+    """Two sites stacked along z with periods (1, 1, 2): each site has one x link
+    and one y link to itself and the two sites share two z links, so
+    Z = sum_{s0,s1} W[s0,s0]^2 W[s1,s1]^2 W[s0,s1]^2 = e^{4b} (2 e^{2b} + 2 e^{-2b})."""
+    O = model.pepo_O(beta)
+    Z = np.einsum("pqlulu,qpmvmv->", O, O)
+    assert np.isclose(Z, np.exp(4 * beta) * (2 * np.exp(2 * beta) + 2 * np.exp(-2 * beta)), rtol=1e-13)
+
+
+# ------------------------------------------------------------------- D4 ansatz
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_d4_projection_rank_and_idempotence(D):
+    """Burnside: the D4-invariant subspace of C^2 (x) (C^D)^(x4) under leg
+    permutations has dimension 2 (D^4 + 2 D^3 + 3 D^2 + 2 D) / 8."""
+    n = 2 * D ** 4
+    M = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        M[:, k] = model.d4_symmetrize(e.reshape(2, D, D, D, D)).ravel()
+    assert np.allclose(M @ M, M, atol=1e-14)
+    assert np.allclose(M, M.T, atol=1e-14)
+    rank = int(round(np.trace(M)))
+    assert rank == 2 * (D ** 4 + 2 * D ** 3 + 3 * D ** 2 + 2 * D) // 8
+
+
+def test_d4_symmetric_tensor_invariant_under_every_group_element():
+    A = model.d4_symmetrize(raw_peps(3, 5))
+    # generators of D4 acting on (l,u,r,d): quarter turn and one reflection
+    rot = A.transpose(0, 2, 3, 4, 1)
+    ref = A.transpose(0, 3, 2, 1, 4)
+    assert np.allclose(rot, A, atol=1e-15) and np.allclose(ref, A, atol=1e-15)
+
+
+# -------------------------------------------------------------- Onsager (2D)
+
+@pytest.mark.parametrize("beta", [0.18, 0.2, 0.26])
+def test_onsager_two_forms_agree(beta):
+    assert abs(exact.onsager_log_kappa(beta) - exact.onsager_log_kappa_double(beta)) < 1e-12
+
+
+@pytest.mark.parametrize("beta", [0.18, 0.2, 0.26])
+def test_ctm_core_reproduces_onsager(beta):
+    a = model.ising_2d_site(beta)
+    C, T, it, dl = unsplit.run(a, (2,), 32, 400, tol=1e-14)
+    lk, _ = unsplit.log_kappa(C, T, a)
+    assert abs(lk - exact.onsager_log_kappa(beta)) < 1e-12
+
+
+# ------------------------------------------------------ reduced (unsplit) CTM
+
+@pytest.mark.parametrize("sign", [+1, -1])
+@pytest.mark.parametrize("D", [2, 3])
+def test_unsplit_product_state_closed_form(sign, D):
+    beta = 0.2
+    f, _ = unsplit.free_energy(beta, model.embed_product_state(D, sign), 24, 100)
+    assert abs(f - exact.product_state_f(beta, sign)) < 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_unsplit_equals_brute_force_patches(n):
+    """n untruncated steps from the product boundary represent the finite patches
+    exactly: kappa = Z(2n+1,2n+1) Z(2n,2n) / (Z(2n+1,2n) Z(2n,2n+1))."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 0))
+    a3 = model.fuse_triple(A, model.pepo_O(beta))
+    e = unsplit.boundary_vector((2, 2, 2))
+    C, T, _, _ = unsplit.run(a3, (2, 2, 2), 10 ** 6, n)
+    n1, n2, n0 = unsplit.patch_values(C, T, a3)
+    Z = lambda x, y: exact.patch_value(a3, e, x, y)  # noqa: E731
+    kb = Z(2 * n + 1, 2 * n + 1) * Z(2 * n, 2 * n) / (Z(2 * n + 1, 2 * n) * Z(2 * n, 2 * n + 1))
+    assert abs(n1 * n0 / n2 ** 2 / kb - 1) < 1e-12
+
+
+# --------------------------------------------------------------- split CTMRG
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_split_untruncated_equals_unsplit(n):
+    """Without truncation the split environment reproduces the reduced one: same
+    per-site kappa and the same corner eigenvalues (the spectrum of rho_eff up to
+    the bond gauge)."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 0))
+    O = model.pepo_O(beta)
+    a3 = model.fuse_triple(A, O)
+    env, _, _, _ = split.run(A, O, 10 ** 9, n)
+    n1, n2h, n2v, n0 = split.patch_values(env, A, O)
+    C, T, _, _ = unsplit.run(a3, (2, 2, 2), 10 ** 9, n)
+    m1, m2, m0 = unsplit.patch_values(C, T, a3)
+    assert abs(n1 * n0 / (n2h * n2v) / (m1 * m0 / m2 ** 2) - 1) < 1e-12
+    ev_s = np.sort(np.abs(np.linalg.eigvals(split.rho_eff(env))))[::-1]
+    ev_u = np.sort(np.abs(np.linalg.eigvalsh(C)) ** 4)[::-1]
+    k = min(ev_s.size, ev_u.size)
+    ev_s, ev_u = ev_s[:k] / ev_s.sum(), ev_u[:k] / ev_u.sum()
+    big = ev_u > 1e-10
+    assert np.allclose(ev_s[big], ev_u[big], rtol=1e-8)
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_split_product_state_closed_form(sign):
+    beta = 0.2
+    f, _ = split.free_energy(beta, model.embed_product_state(2, sign), 16, 300, tol=1e-13)
+    assert abs(f - exact.product_state_f(beta, sign)) < 1e-8
+
+
+def test_split_converges_to_reduced_method():
+    """Sec. IV A: the split scheme reaches the reduced-method value as chi grows."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 0))
+    f_ref, _ = unsplit.free_energy(beta, A, 48, 100)
+    errs = []
+    for chi in (8, 16, 32):
+        f, _ = split.free_energy(beta, A, chi, 100)
+        errs.append(abs(f - f_ref))
+    assert errs[-1] < 1e-10
+    assert errs[0] > errs[1] > errs[2]
+
+
+def test_split_double_layer_matches_reduced_norm():
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 3))
+    _, info_s = split.free_energy(beta, A, 32, 100)
+    _, info_u = unsplit.free_energy(beta, A, 48, 100)
+    assert abs(info_s["log_kappa2"] - info_u["log_kappa2"]) < 1e-10
+
+
+def test_split_d2_relation_and_projector_identity():
+    """n2 strips agree in both orientations (D2 relations) and every projector
+    pair satisfies P_T P_B = I (Sec. III B)."""
+    beta = 0.22
+    A = model.d4_symmetrize(raw_peps(2, 1))
+    O = model.pepo_O(beta)
+    env, _, _, _ = split.run(A, O, 12, 8)
+    n1, n2h, n2v, n0 = split.patch_values(env, A, O)
+    assert abs(n2h / n2v - 1) < 1e-12
+    assert np.allclose(env["C1"], env["C1"].T) and np.allclose(env["C4"], env["C4"].T)
+    _, projs = split.step(env, A, O, 12)
+    for name, (PT, PB, S) in projs.items():
+        assert np.allclose(PT @ PB, np.eye(PT.shape[0]), atol=1e-9), name
+
+
+def test_split_invariants():
+    """f(cA) = f(A); f is invariant under the spin flip of the physical leg
+    (Ising Z2); <A, g> = 0 (g is the log-derivative difference)."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 4))
+    f, g, _ = split.f_and_grad(beta, A, 12, 60)
+    f2, _ = split.free_energy(beta, 3.7 * A, 12, 60)
+    f3, _ = split.free_energy(beta, A[::-1].copy(), 12, 60)
+    assert abs(f2 - f) < 1e-11 and abs(f3 - f) < 1e-11
+    assert abs(np.sum(A * g)) < 1e-12 * np.linalg.norm(A) * np.linalg.norm(g) * 100
+
+
+def test_split_gradient_central_differences():
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 0))
+    f, g, _ = split.f_and_grad(beta, A, 16, 300, tol=1e-13)
+    h = 1e-5
+    for v in random_directions(A.shape, 2, 11):
+        v = model.d4_symmetrize(v)
+        v /= np.linalg.norm(v)
+        fp, _ = split.free_energy(beta, A + h * v, 16, 300, tol=1e-13)
+        fm, _ = split.free_energy(beta, A - h * v, 16, 300, tol=1e-13)
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - np.sum(g * v)) < 1e-5 * abs(fd)
+
+
+def test_split_gradient_matches_reduced_gradient():
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 0))
+    _, g_s, _ = split.f_and_grad(beta, A, 32, 100)
+    _, g_u, _ = unsplit.f_and_grad(beta, A, 48, 100)
+    assert np.linalg.norm(g_s - g_u) < 1e-8 * np.linalg.norm(g_u)
