@@ -55,6 +55,7 @@ from . import model
 
 SVD_CUTOFF = 1e-12
 GROW_CHI = 1 << 30   # "no truncation" for the first move
+LAST_STAGE2_ENVS = {}  # rho_T / rho_B of P5 and P6 from the last stage2 call
 
 
 # ----------------------------------------------------------------------------
@@ -298,7 +299,7 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
     UL = ein("wobcpgr,ecob->wepgr", UL, P2T)              # -> [s3,c2L,p1,Ad1,Ar1]
     X = ein("wus,sot,tbv,vz->wuobz", Tk, Ti, Tb, C4)      # top cell 2 + C2 (= C4)
     X = ein("wuobz,zrh->wuobrh", X, Rk)                   # right Tk'
-    UR = ein("wuobrh,plugr->wlgpobh", X, A)               # [s3,Al2,Ad2,p2,Ou2,Bu2,rkb]
+    UR = ein("wuobrh,plurg->wlgpobh", X, A)               # [s3,Al2,Ad2,p2,Ou2,Bu2,rkb]
     # P2^R_T[c,(chi,a,p)] = P3B[(chi,a,p),c]
     UR = ein("wlgpobh,hgpe->wlobe", UR, P3B)              # [s3,Al2,Ou2,Bu2,c2R]
     rhoT5 = ein("wepgr,wrobf->egpobf", UL, UR)            # [c2L,Ad1,p1,Ou2,Bu2,c2R]
@@ -329,7 +330,7 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
     UL6 = ein("wbjqgref,cjbq->wcgref", UL6, P3T)          # [s3,c3L,Ad1,Ar1,Or1,Od1]
     X = ein("wus,sot,tbv,vz->wuobz", Tk, Ti, Tb, C4)
     X = ein("wuobz,zrh->wuobrh", X, Rk)
-    X = ein("wuobrh,plugr->wlgpobh", X, A)                # [s3,Al2,Ad2,p2,Ou2,Bu2,rkb]
+    X = ein("wuobrh,plurg->wlgpobh", X, A)                # [s3,Al2,Ad2,p2,Ou2,Bu2,rkb]
     X = ein("wlgpobh,hsk->wlgpobsk", X, Ri)               # right Ti', s=Or2
     UR6 = ein("wlgpobsk,pqmost->wlgbkqmt", X, O)          # [s3,Al2,Ad2,Bu2,rib,q2,Ol2,Od2]
     # P3^R_T[c,(chi,o,a)] = P2B[(chi,o,a),c]
@@ -348,6 +349,8 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
     rhoB6 = ein("eyaov,fqyuv->eaouqf", LL6, LR6)          # [c3L,Ad1,Od1,Bu2,q2,c3R]
     n6 = rhoT6.shape[0] * D * d
     P6 = projector_pair(rhoB6.reshape(n6, -1).T, rhoT6.reshape(n6, -1), chi, cutoff)
+    LAST_STAGE2_ENVS.clear()
+    LAST_STAGE2_ENVS.update(rhoT5=rhoT5, rhoB5=rhoB5, rhoT6=rhoT6, rhoB6=rhoB6)
     return P4, P5, P6, C1p, C4p
 
 

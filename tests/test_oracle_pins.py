@@ -218,3 +218,25 @@ def test_split_gradient_matches_reduced_gradient():
     _, g_s, _ = split.f_and_grad(beta, A, 32, 100)
     _, g_u, _ = unsplit.f_and_grad(beta, A, 48, 100)
     assert np.linalg.norm(g_s - g_u) < 1e-8 * np.linalg.norm(g_u)
+
+
+def test_split_halves_are_related_by_the_180_degree_rotation():
+    """Eq. (Symmetry constraints): the 180-degree rotation about the PEPO site
+    swaps ket and bra, left and right, up and down.  It maps every upper half
+    used for a projector onto the matching lower half, so these pairs must be
+    index permutations of each other."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(3, 0))
+    O = model.pepo_O(beta)
+    env, _, _, _ = split.run(A, O, 20, 4)
+    up_ki, up_ib, up_bk = split.upper_sequence(env, A, O)
+    lo_ki, lo_ib, lo_bk = split.lower_sequence(env, A, O)
+    rel = lambda x, y: np.linalg.norm(x - y) / np.linalg.norm(y)  # noqa: E731
+    assert rel(lo_bk, up_bk.transpose(4, 1, 2, 3, 0)) < 1e-13
+    assert rel(lo_ib, np.einsum("fqbeca->aqbcef", up_ki)) < 1e-13
+    assert rel(lo_ki, np.einsum("fpobca->apobcf", up_ib)) < 1e-13
+    P1, P2, P3 = split.stage1(env, A, O, 20)
+    split.stage2(env, A, O, 20, P1, P2, P3)
+    E = split.LAST_STAGE2_ENVS
+    assert rel(E["rhoB5"], np.einsum("gfebca->abcefg", E["rhoT6"])) < 1e-13
+    assert rel(E["rhoB6"], np.einsum("gefcba->abcefg", E["rhoT5"])) < 1e-13
