@@ -1,0 +1,134 @@
+/*
+ * ctm.h -- C ABI of the split-CTMRG library (libctm.so, HIP / gfx950).
+ *
+ * The library contracts the two infinite networks of the variational iPEPS
+ * method for 3D classical models -- the triple-layer <psi(A)|T|psi(A)> with the
+ * 3D Ising PEPO T, and the double-layer norm <psi(A)|psi(A)> -- with the split
+ * corner-transfer-matrix renormalisation group, and returns the free-energy
+ * density f(beta, A) of Eq. (free energy expression) and its gradient g of
+ * Eq. (gradient expression).
+ *
+ *   environment    Sec. III A: corners C_i and one edge tensor per layer
+ *                  (T^ket, T^int, T^bra); the D2 relations of Eq. (Symmetry
+ *                  constraints) leave C1 (= C3), C4 (= C2) and the left-edge
+ *                  chain as the stored state.
+ *   one iteration  Sec. III B: absorption of one column into all four
+ *                  directions at once, two-stage truncation of every bond with
+ *                  six projector pairs (P1..P3 bra-related, P4..P6 ket-related),
+ *                  built as in Sec. III C and the Appendix (six-projector scheme).
+ *   convergence    Sec. III D: l2 change of the singular values of
+ *                  C1 C2 C3 C4 / Tr(C1 C2 C3 C4).
+ *
+ * Layouts.  The PEPS tensor A and the gradient g are dense float64 arrays of
+ * 2 * D^4 entries, row-major over [p][l][u][r][d] (p physical, then the four
+ * virtual legs left, up, right, down).  A is copied at init; the caller keeps
+ * ownership of every pointer it passes.  Pointers are host pointers unless
+ * cfg->flags has CTM_FLAG_DEVICE_PTRS set, in which case A and g are device
+ * pointers on the current HIP device.
+ *
+ * Streams.  All device work of a context is enqueued on the hip_stream given at
+ * init (NULL = the legacy default stream).  Calls that return host values
+ * (ctm_iterate's delta, ctm_free_energy, ctm_grad with host g, spectra)
+ * synchronise that stream.  A context must be used by one host thread at a
+ * time; distinct contexts are independent.
+ *
+ * Errors.  Every call returns a ctm_status; nothing is thrown across the ABI.
+ * ctm_last_error() gives a message for the last failing call on a context.
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTM_ABI_VERSION 1
+
+typedef struct ctm_ctx ctm_ctx;
+
+typedef enum {
+    CTM_OK = 0,
+    CTM_EINVAL = 1,     /* bad argument: beta <= 0, D < 1, chi < 1, NULL ... */
+    CTM_ENOMEM = 2,     /* device allocation failed                           */
+    CTM_EDEVICE = 3,    /* a HIP call failed                                  */
+    CTM_ENOCONV = 4,    /* max_iter reached before tol; results stay readable */
+    CTM_ENUMERIC = 5,   /* NaN/Inf or a non-positive network value            */
+    CTM_ESTATE = 6      /* call out of order (e.g. f before any iteration)    */
+} ctm_status;
+
+typedef enum {
+    CTM_FP64 = 0,       /* every contraction in float64                          */
+    CTM_FP32 = 1,       /* bulk contractions float32 in / float32 accumulate;    */
+                        /* projector factorisations, norms, f, g stay float64    */
+    CTM_BF16 = 2        /* bulk contractions bfloat16 in / float32 accumulate    */
+} ctm_precision;
+
+#define CTM_FLAG_DEVICE_PTRS 1
+
+typedef struct {
+    int D;              /* PEPS virtual bond dimension, 1 <= D <= 8               */
+    int chi;            /* environment bond dimension, 1 <= chi <= 512            */
+    int max_iter;       /* cap used by ctm_iterate(n_iter <= 0)                   */
+    double tol;         /* convergence threshold on the spectrum change (>= 0)    */
+    int precision;      /* ctm_precision of the bulk contractions                 */
+    int flags;          /* CTM_FLAG_* bits                                        */
+    int power_iters;    /* subspace iterations of the projector SVD (0: default)  */
+    double svd_cutoff;  /* relative singular-value cutoff (0: default 1e-12)      */
+} ctm_config;
+
+/* Build a context: the PEPO O of the 3D Ising model at inverse temperature
+ * beta (Sec. IV: O = delta grouped with six sqrt(W) factors), the D4 projection
+ * of A (Sec. III B), and the product-boundary initial environments of both
+ * networks.  beta must be > 0.  On success *out owns all device memory it
+ * allocates; release it with ctm_destroy.  On failure *out is NULL. */
+ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A,
+                    void* hip_stream, ctm_ctx** out);
+
+/* Run n_iter split-CTMRG iterations on both networks (n_iter <= 0: iterate
+ * until the spectrum change of both networks is below cfg->tol or max_iter
+ * iterations have been done in total; then CTM_ENOCONV if tol was not met).
+ * iters_done (may be NULL) receives the iterations done by this call and
+ * last_delta (may be NULL) the larger of the two spectrum changes of the last
+ * iteration. */
+ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_delta);
+
+/* f = -(ln kappa3 - ln kappa2) / beta with the per-site values kappa of the
+ * triple- and double-layer networks estimated as n1 n0 / (n2h n2v) from the
+ * current environments (Eq. free energy expression).  Any output pointer may be
+ * NULL.  CTM_ESTATE before the first iteration. */
+ctm_status ctm_free_energy(ctm_ctx* c, double* f, double* log_kappa3, double* log_kappa2);
+
+/* g = -(2/beta) (E3/n1_3 - E2/n1_2), the environment of the bra tensor in the
+ * 3x3 patch of each network normalised by that patch's value, projected onto
+ * the D4-symmetric subspace (Eq. gradient expression).  g has 2 D^4 entries in
+ * the layout of A (host or device per CTM_FLAG_DEVICE_PTRS). */
+ctm_status ctm_grad(ctm_ctx* c, double* g);
+
+/* Singular values of C1 C2 C3 C4 / |Tr(C1 C2 C3 C4)| for network which = 3
+ * (triple layer) or 2 (double layer), descending; *n receives the count
+ * (<= cap).  Host buffer. */
+ctm_status ctm_corner_spectrum(ctm_ctx* c, int which, double* s, int cap, int* n);
+
+/* Replace beta and A and keep the converged environments as the starting
+ * point of the next ctm_iterate (warm restart). */
+ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A);
+
+/* Iterations done so far, and the device bytes the context holds. */
+ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes);
+
+/* Release a context.  NULL-safe. */
+void ctm_destroy(ctm_ctx* c);
+
+/* Message of the last failing call on c (or of the last failing ctm_init when
+ * c is NULL).  Never NULL. */
+const char* ctm_last_error(const ctm_ctx* c);
+
+const char* ctm_status_string(int status);
+
+int ctm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTM_H */

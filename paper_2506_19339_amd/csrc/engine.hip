@@ -1,0 +1,938 @@
+// Host side of the split-CTMRG library: context state, a small contraction
+// engine (labelled pairwise contractions -> permute + batched MFMA GEMM), the
+// projector construction, one symmetric split-CTMRG iteration, the free-energy
+// and gradient contractions, and the C ABI declared in include/ctm.h.
+//
+// Method (paper passages):
+//   * split environment and its D2 relations        Sec. III A, Eq. (Symmetry constraints)
+//   * left move: insert, absorb, truncate with six
+//     projector pairs, bra-related stage first        Sec. III B
+//   * projector pair from rho_B rho_T = U S V:
+//     P_B = rho_T V^+ S^-1/2, P_T = S^-1/2 U^+ rho_B  Sec. III C, Eqs. (projector construction)
+//   * P1 (one column, two rows), P2 / P3 (1x1 cell),
+//     half P4 (two enlarged corners renormalised by
+//     P1 and its up/down images), P5 / P6 (two
+//     columns, renormalised by P2, P2^R / P3, P3^R)  Appendix, six-projector scheme
+//   * convergence on the spectrum of C1C2C3C4/Tr      Sec. III D
+//   * f and g from the 3x3 patch                      Eqs. (free energy / gradient expression)
+//
+// Layout of the stored state (row-major, float64, device):
+//   C1[x][y]   (x -> top edge, y -> left edge)      C4[x][y] (x -> left edge, y -> bottom edge)
+//   Tk[a][m][b], Ti[a][m][b], Tb[a][m][b]           left-edge chain, a up, m into the bulk, b down
+//   the right / bottom edges are the transposes Tb^T, Ti^T, Tk^T (D2 relations), C2 = C4, C3 = C1.
+// The bond between Tb and the next Tk (and every corner leg) is "bk", between Tk
+// and Ti "ki", between Ti and Tb "ib".
+//
+// The lower halves of the projector environments are never contracted: the
+// 180-degree rotation about the PEPO site (ket <-> bra, left <-> right, up <->
+// down) maps each upper half onto the matching lower half, so they are index
+// permutations of the upper ones.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ctm.h"
+#include "kernels.h"
+
+namespace {
+
+struct CtmError : std::runtime_error {
+    int code;
+    CtmError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess)                                                                  \
+            throw CtmError(e_ == hipErrorOutOfMemory ? CTM_ENOMEM : CTM_EDEVICE,               \
+                           std::string(#x) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+#define REQUIRE(cond, msg)                                                                     \
+    do {                                                                                       \
+        if (!(cond)) throw CtmError(CTM_EINVAL, std::string("internal: ") + (msg));           \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory: a chunked bump arena (stack discipline via mark / release)
+// ---------------------------------------------------------------------------
+class Arena {
+    struct Chunk { char* p; size_t cap; };
+    std::vector<Chunk> ch_;
+    size_t cur_ = 0, off_ = 0;
+
+public:
+    struct Mark { size_t cur, off; };
+    size_t bytes_held = 0;
+
+    Mark mark() const { return {cur_, off_}; }
+    void release(Mark m) { cur_ = m.cur; off_ = m.off; }
+
+    double* alloc(int64_t count)
+    {
+        size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(double);
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (;;) {
+            if (cur_ < ch_.size()) {
+                if (off_ + bytes <= ch_[cur_].cap) {
+                    char* r = ch_[cur_].p + off_;
+                    off_ += bytes;
+                    return (double*)r;
+                }
+                if (cur_ + 1 < ch_.size()) { ++cur_; off_ = 0; continue; }
+            }
+            size_t sz = std::max(bytes, (size_t)128 << 20);
+            void* p = nullptr;
+            hipError_t e = hipMalloc(&p, sz);
+            if (e != hipSuccess) throw CtmError(CTM_ENOMEM, "workspace allocation failed");
+            ch_.push_back({(char*)p, sz});
+            bytes_held += sz;
+            cur_ = ch_.size() - 1;
+            off_ = 0;
+        }
+    }
+
+    void free_all()
+    {
+        for (auto& c : ch_) (void)hipFree(c.p);
+        ch_.clear();
+        cur_ = off_ = 0;
+        bytes_held = 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// dense tensor handle (device buffer + row-major dims)
+// ---------------------------------------------------------------------------
+constexpr int kMaxRank = 12;
+
+struct Tn {
+    double* p = nullptr;
+    int r = 0;
+    int64_t d[kMaxRank] = {0};
+    int64_t n() const
+    {
+        int64_t s = 1;
+        for (int i = 0; i < r; ++i) s *= d[i];
+        return s;
+    }
+};
+
+static Tn make_tn(double* p, std::initializer_list<int64_t> dims)
+{
+    Tn t;
+    t.p = p;
+    for (int64_t v : dims) t.d[t.r++] = v;
+    return t;
+}
+
+struct Projector {
+    Tn PT;   // k x trunc
+    Tn PB;   // trunc x k
+    int k = 0;
+};
+
+// one network (triple layer: PEPO d = 2; double layer: delta PEPO, d = 1)
+struct Net {
+    int d = 2;
+    double* O = nullptr;             // [2][2][d][d][d][d]
+    double *C1 = nullptr, *C4 = nullptr, *Tk = nullptr, *Ti = nullptr, *Tb = nullptr;
+    int64_t xbk = 1, xki = 1, xib = 1;
+    double* s_old = nullptr;         // previous normalised spectrum
+    int* n_old = nullptr;
+    double* delta = nullptr;         // last spectrum change
+    double* sc = nullptr;            // scalars: n1 n2h n2v n0 | lk flag | tr
+    double* E = nullptr;             // bra environment, 2 D^4
+    double* sv = nullptr;            // spectrum buffer
+};
+
+constexpr int kJacobiExact = 256;   // exact Jacobi SVD up to this min(m, n)
+constexpr int kOversample = 16;
+constexpr int kJacobiSweeps = 40;
+
+}  // namespace
+
+struct ctm_ctx {
+    ctm_config cfg{};
+    double beta = 0.0;
+    int D = 0, chi = 0, xmax = 0;
+    hipStream_t st = nullptr;
+    int device = 0;
+    Arena ws;
+    std::vector<void*> owned;        // persistent allocations
+    double* A = nullptr;             // D4-projected A, [2][D][D][D][D]
+    double* part = nullptr;          // reduction partials
+    double* scal = nullptr;          // scratch scalars
+    int* icount = nullptr;           // device int for rank read-back
+    Net net[2];                      // [0] triple, [1] double
+    int iters = 0;
+    uint64_t svd_calls = 0;
+    std::string err;
+
+    // ---------------- allocation helpers
+    double* keep(int64_t count)
+    {
+        void* p = nullptr;
+        HIPCHK(hipMalloc(&p, (size_t)std::max<int64_t>(count, 1) * sizeof(double)));
+        owned.push_back(p);
+        return (double*)p;
+    }
+    Tn tmp(std::initializer_list<int64_t> dims)
+    {
+        Tn t;
+        for (int64_t v : dims) t.d[t.r++] = v;
+        t.p = ws.alloc(t.n());
+        return t;
+    }
+    Tn tmp_dims(const int64_t* dims, int r)
+    {
+        Tn t;
+        t.r = r;
+        for (int i = 0; i < r; ++i) t.d[i] = dims[i];
+        t.p = ws.alloc(t.n());
+        return t;
+    }
+
+    // ---------------- contraction engine
+    // permute(A, "abc->cab")
+    Tn perm(const Tn& A, const char* spec)
+    {
+        std::string s(spec);
+        const size_t ar = s.find("->");
+        REQUIRE(ar != std::string::npos, spec);
+        const std::string li = s.substr(0, ar), lo = s.substr(ar + 2);
+        REQUIRE((int)li.size() == A.r && lo.size() == li.size(), spec);
+        return permute_labels(A, li, lo);
+    }
+
+    Tn permute_labels(const Tn& A, const std::string& li, const std::string& lo)
+    {
+        if (li == lo) return A;
+        REQUIRE(A.r <= kMaxRank, "rank too large");
+        int64_t istride[kMaxRank];
+        int64_t acc = 1;
+        for (int k = A.r - 1; k >= 0; --k) { istride[k] = acc; acc *= A.d[k]; }
+        ctmk::PermDesc pd{};
+        pd.rank = A.r;
+        int64_t od[kMaxRank];
+        for (int k = 0; k < A.r; ++k) {
+            const size_t pos = li.find(lo[k]);
+            REQUIRE(pos != std::string::npos, "permute label");
+            od[k] = A.d[pos];
+            pd.od[k] = od[k];
+            pd.is[k] = istride[pos];
+        }
+        Tn out = tmp_dims(od, A.r);
+        ctmk::permute(st, A.p, out.p, pd, out.n());
+        return out;
+    }
+
+    static Tn view(const Tn& A, std::initializer_list<int64_t> dims)
+    {
+        Tn t;
+        t.p = A.p;
+        for (int64_t v : dims) t.d[t.r++] = v;
+        if (t.n() != A.n()) throw CtmError(CTM_EINVAL, "internal: view size mismatch");
+        return t;
+    }
+
+    // ctr("ab,bc->ac", A, B): labelled pairwise contraction.  Labels shared by
+    // A, B and the output are batch labels; shared by A and B only are summed.
+    Tn ctr(const char* spec, const Tn& A, const Tn& B)
+    {
+        std::string s(spec);
+        const size_t cm = s.find(','), ar = s.find("->");
+        REQUIRE(cm != std::string::npos && ar != std::string::npos, spec);
+        const std::string la = s.substr(0, cm), lb = s.substr(cm + 1, ar - cm - 1), lo = s.substr(ar + 2);
+        REQUIRE((int)la.size() == A.r && (int)lb.size() == B.r, spec);
+        int64_t dim[128];
+        for (int i = 0; i < 128; ++i) dim[i] = -1;
+        for (int i = 0; i < A.r; ++i) dim[(int)la[i]] = A.d[i];
+        for (int i = 0; i < B.r; ++i) {
+            const int c = (int)lb[i];
+            REQUIRE(dim[c] < 0 || dim[c] == B.d[i], std::string("dimension mismatch in ") + spec);
+            dim[c] = B.d[i];
+        }
+        std::string bt, con, fa, fb;
+        for (char c : la) {
+            const bool inB = lb.find(c) != std::string::npos, inO = lo.find(c) != std::string::npos;
+            if (inB && inO) bt += c;
+            else if (inB) con += c;
+            else if (inO) fa += c;
+            else REQUIRE(false, std::string("label summed out of one operand in ") + spec);
+        }
+        for (char c : lb)
+            if (la.find(c) == std::string::npos) {
+                REQUIRE(lo.find(c) != std::string::npos, spec);
+                fb += c;
+            }
+        REQUIRE(lo.size() == bt.size() + fa.size() + fb.size(), spec);
+        // contracted order: A's if A needs no permute, else B's if B needs none
+        auto in_order = [](const std::string& lab, const std::string& sub) {
+            std::string r;
+            for (char c : lab)
+                if (sub.find(c) != std::string::npos) r += c;
+            return r;
+        };
+        std::string conA = in_order(la, con), conB = in_order(lb, con);
+        std::string fbB = in_order(lb, fb);
+        const std::string faA = in_order(la, fa);
+        bool tA = false, tB = false, okA = false, okB = false;
+        std::string cord = conA;
+        if (la == bt + faA + conA) { okA = true; tA = false; }
+        else if (la == bt + conA + faA) { okA = true; tA = true; }
+        if (!okA) {
+            const std::string btB = in_order(lb, bt);
+            if (btB == bt && (lb == bt + conB + fbB || lb == bt + fbB + conB)) cord = conB;
+        }
+        if (lb == bt + cord + fbB) { okB = true; tB = false; }
+        else if (lb == bt + fbB + cord) { okB = true; tB = true; }
+        Tn Ao = A, Bo = B;
+        if (!okA) { Ao = permute_labels(A, la, bt + faA + cord); tA = false; }
+        if (!okB) { Bo = permute_labels(B, lb, bt + cord + fbB); tB = false; }
+        int64_t M = 1, N = 1, K = 1, nb = 1;
+        for (char c : faA) M *= dim[(int)c];
+        for (char c : fbB) N *= dim[(int)c];
+        for (char c : cord) K *= dim[(int)c];
+        for (char c : bt) nb *= dim[(int)c];
+        const std::string nat = bt + faA + fbB;
+        REQUIRE((int)nat.size() <= kMaxRank, "rank too large");
+        int64_t od[kMaxRank];
+        int orank = 0;
+        for (char c : nat) od[orank++] = dim[(int)c];
+        Tn C = tmp_dims(od, orank);
+        if (M == 1 && N == 1 && nb == 1) {
+            ctmk::dot(st, Ao.p, Bo.p, K, C.p, part, 0);
+        } else {
+            REQUIRE(M < INT_MAX && N < INT_MAX && K < INT_MAX, "GEMM too large");
+            ctmk::gemm_f64(st, tA, tB, (int)M, (int)N, (int)K, 1.0,
+                           Ao.p, tA ? M : K, M * K, Bo.p, tB ? K : N, K * N,
+                           0.0, C.p, N, M * N, (int)nb);
+        }
+        if (lo == nat) return C;
+        return permute_labels(C, nat, lo);
+    }
+
+    // ---------------- dense linear algebra on row-major matrices
+    // C[M][N] = op(A) op(B)
+    Tn mm(const Tn& A, bool ta, const Tn& B, bool tb)
+    {
+        const int64_t M = ta ? A.d[1] : A.d[0], K = ta ? A.d[0] : A.d[1];
+        const int64_t K2 = tb ? B.d[1] : B.d[0], N = tb ? B.d[0] : B.d[1];
+        REQUIRE(A.r == 2 && B.r == 2 && K == K2, "mm shapes");
+        Tn C = tmp({M, N});
+        ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A.p, A.d[1], 0, B.p, B.d[1], 0,
+                       0.0, C.p, N, 0, 1);
+        return C;
+    }
+
+    // Jacobi SVD of X given as an m x n column-major matrix (n columns).
+    // Returns U (m x n col-major), V (n x n col-major), S (n): X = U S V^T.
+    void jacobi(const Tn& Xcm, int64_t m, int64_t n, Tn& U, Tn& V, Tn& S)
+    {
+        REQUIRE(n <= 1024, "Jacobi: too many columns");
+        Tn X = tmp({n, m});
+        ctmk::copy(st, Xcm.p, X.p, m * n);
+        Tn W = tmp({n, n});
+        U = tmp({n, m});
+        V = tmp({n, n});
+        S = tmp({n});
+        ctmk::JacobiBatch jb{};
+        jb.n = 1;
+        jb.job[0] = ctmk::JacobiJob{X.p, W.p, U.p, V.p, S.p, (int)m, (int)n};
+        ctmk::jacobi_svd(st, jb, kJacobiSweeps);
+    }
+
+    // rows of Yt (k x L) -> orthonormal rows spanning the same space (SVQB):
+    // G = Yt Yt^T = V L V^T, Q^T = L^-1/2 V^T Yt, directions with tiny L dropped.
+    Tn svqb(const Tn& Yt)
+    {
+        const int64_t k = Yt.d[0];
+        Tn G = mm(Yt, false, Yt, true);
+        Tn U, V, S;
+        jacobi(G, k, k, U, V, S);
+        Tn f = tmp({k});
+        ctmk::inv_sqrt_cut(st, S.p, f.p, (int)k, 1e-26);
+        // V col-major k x k == V^T row-major
+        Tn Vt = make_tn(V.p, {k, k});
+        Tn Q = mm(Vt, false, Yt, false);
+        ctmk::scale_lines(st, Q.p, (int)k, (int)Q.d[1], f.p, 0);
+        return Q;
+    }
+
+    // top-kk singular triplets of M (m x n row-major): UT (kk x m), S (kk), VT (kk x n)
+    void svd_topk(const Tn& M, int64_t kk, Tn& UT, Tn& S, Tn& VT)
+    {
+        const int64_t m = M.d[0], n = M.d[1], mn = std::min(m, n);
+        Tn U, V, Sv;
+        if (mn <= kJacobiExact) {
+            if (m <= n) {
+                // M row-major == M^T column-major (n rows, m columns)
+                jacobi(M, n, m, U, V, Sv);
+                // M = V S U^T : left vectors = columns of V (m), right = columns of U (n)
+                UT = make_tn(V.p, {kk, m});
+                VT = make_tn(U.p, {kk, n});
+            } else {
+                Tn Mt = perm(M, "ab->ba");   // M^T row-major == M column-major (m rows, n cols)
+                jacobi(Mt, m, n, U, V, Sv);
+                UT = make_tn(U.p, {kk, m});
+                VT = make_tn(V.p, {kk, n});
+            }
+            S = make_tn(Sv.p, {kk});
+            return;
+        }
+        const int64_t k = std::min<int64_t>(kk + kOversample, mn);
+        Tn Pt = tmp({k, n});
+        ctmk::randn(st, Pt.p, k * n, 0x5eedull + 7919ull * (++svd_calls));
+        const int q = cfg.power_iters > 0 ? cfg.power_iters : 4;
+        Pt = svqb(Pt);
+        for (int it = 0; it < q; ++it) {
+            Tn Yt = mm(Pt, false, M, true);       // (M P)^T
+            Tn Qt = svqb(Yt);
+            Tn Zt = mm(Qt, false, M, false);      // (M^T Q)^T
+            Pt = svqb(Zt);
+        }
+        Pt = svqb(Pt);
+        Tn Yt = mm(Pt, false, M, true);
+        Tn Qt = svqb(svqb(Yt));
+        Tn X1 = mm(Qt, false, M, false);          // Q^T M   (k x n)
+        Tn Bs = mm(X1, false, Pt, true);          // Q^T M P (k x k)
+        // Bs row-major == Bs^T col-major: Bs^T = Uj S Vj^T -> Bs = Vj S Uj^T
+        jacobi(Bs, k, k, U, V, Sv);
+        Tn Vjt = make_tn(V.p, {k, k});            // rows = left vectors of Bs
+        Tn Ujt = make_tn(U.p, {k, k});            // rows = right vectors of Bs
+        Tn UTf = mm(Vjt, false, Qt, false);       // (Q Us)^T
+        Tn VTf = mm(Ujt, false, Pt, false);       // (P Vs)^T
+        UT = make_tn(UTf.p, {kk, m});
+        VT = make_tn(VTf.p, {kk, n});
+        S = make_tn(Sv.p, {kk});
+    }
+
+    // projector pair from rhoT (t x rT) and rhoB (rB x t)
+    Projector projector(const Tn& rT, const Tn& rB, int64_t chi)
+    {
+        const int64_t t = rT.d[0], remT = rT.d[1], remB = rB.d[0];
+        REQUIRE(rT.r == 2 && rB.r == 2 && rB.d[1] == t, "projector shapes");
+        Projector P;
+        if (t <= chi) {
+            Tn I = tmp({t, t});
+            ctmk::eye(st, I.p, (int)t);
+            P.PT = I;
+            P.PB = I;
+            P.k = (int)t;
+            return P;
+        }
+        Tn M = mm(rB, false, rT, false);          // remB x remT
+        const int64_t k0 = std::min<int64_t>(chi, std::min(remB, remT));
+        Tn UT, S, VT;
+        svd_topk(M, k0, UT, S, VT);
+        // the bond keeps the chi largest singular values that are above the
+        // relative cutoff (its numerical rank): one small read-back
+        const double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : 1e-12;
+        ctmk::count_above(st, S.p, (int)k0, cut, icount);
+        int rank = 0;
+        HIPCHK(hipMemcpyAsync(&rank, icount, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int64_t kk = std::max<int64_t>(1, std::min<int64_t>(k0, rank));
+        UT.d[0] = kk;
+        VT.d[0] = kk;
+        Tn f = tmp({kk});
+        ctmk::inv_sqrt_cut(st, S.p, f.p, (int)kk, cut);
+        P.PB = mm(rT, false, VT, true);           // t x kk
+        ctmk::scale_lines(st, P.PB.p, (int)t, (int)kk, f.p, 1);
+        P.PT = mm(UT, false, rB, false);          // kk x t
+        ctmk::scale_lines(st, P.PT.p, (int)kk, (int)t, f.p, 0);
+        P.k = (int)kk;
+        return P;
+    }
+
+    void normalize(Tn& X)
+    {
+        ctmk::dot(st, X.p, X.p, X.n(), scal, part, 1);
+        ctmk::scale_inv(st, X.p, X.n(), scal);
+    }
+
+    // ---------------- one symmetric split-CTMRG iteration of one network
+    void step(Net& N, int64_t chi);
+    void values(Net& N, double* sc_out, bool with_env);
+};
+
+// --------------------------------------------------------------------------
+// the iteration
+// --------------------------------------------------------------------------
+void ctm_ctx::step(Net& N, int64_t chi)
+{
+    const int64_t D = this->D, d = N.d, P = 2;
+    const Arena::Mark mk = ws.mark();
+    Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
+    Tn K = make_tn(N.Tk, {N.xbk, D, N.xki});
+    Tn I = make_tn(N.Ti, {N.xki, d, N.xib});
+    Tn Bt = make_tn(N.Tb, {N.xib, D, N.xbk});
+    Tn A = make_tn(this->A, {P, D, D, D, D});
+    Tn O = make_tn(N.O, {P, P, d, d, d, d});
+    // right / bottom edge chain (D2 relations)
+    Tn Rk = perm(Bt, "bma->amb"), Ri = perm(I, "bma->amb"), Rb = perm(K, "bma->amb");
+
+    // ---- top row C1 T1(k,i,b) C2 and the upper halves at ki, ib, bk
+    Tn H = ctr("xy,xkc->ykc", C1, K);
+    H = ctr("ykc,cie->ykie", H, I);
+    Tn TRpre = ctr("ykie,ebf->ykibf", H, Bt);          // [y1, Au, Ou, Bu, s3]
+    Tn TR = ctr("ykibf,fz->ykibz", TRpre, C4);          // [y1, Au, Ou, Bu, y2]
+    Tn U = ctr("ykibz,ylg->glkibz", TR, K);
+    U = ctr("glkibz,plkrn->gpnribz", U, A);
+    Tn upki = ctr("gpnribz,zrh->gpnibh", U, Rk);        // [tkb, p, Ad, Ou, Bu, rkb]
+    U = ctr("gpnibh,gmj->jmpnibh", upki, I);
+    U = ctr("jmpnibh,pqmist->jqtsnbh", U, O);
+    Tn upib = ctr("jqtsnbh,hsk->jqtnbk", U, Ri);        // [tib, q, Od, Ad, Bu, rib]
+    U = ctr("jqtnbk,jwv->vwqtnbk", upib, Bt);
+    U = ctr("vwqtnbk,qwbse->vsetnk", U, A);
+    Tn upbk = ctr("vsetnk,ksz->vetnz", U, Rb);          // [tbb, Bd, Od, Ad, rbb]
+
+    // ---- stage 1: P1 (bk, trunc (chi, B)), P2 (ki, (chi, O, B)), P3 (ib, (chi, B, q))
+    const int64_t xbk = N.xbk, xki = N.xki, xib = N.xib;
+    Tn rT1 = perm(upbk, "vetnz->ventz");
+    Tn rB1 = perm(upbk, "fbcea->bcfae");
+    Projector P1 = projector(view(rT1, {xbk * D, D * d * xbk}), view(rB1, {D * d * xbk, xbk * D}), chi);
+    Tn rT2 = perm(upki, "gpnibh->gibnph");
+    Tn rB2 = perm(upib, "jqtnbk->bqjktn");
+    Projector P2 = projector(view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D}), chi);
+    Tn rT3 = perm(upib, "jqtnbk->jbqntk");
+    Tn rB3 = perm(upki, "gpnibh->bighnp");
+    Projector P3 = projector(view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P}), chi);
+    const int64_t c1 = P1.k, c2 = P2.k, c3 = P3.k;
+    Tn P1T = view(P1.PT, {c1, xbk, D}), P1B = view(P1.PB, {xbk, D, c1});
+    Tn P2T = view(P2.PT, {c2, xki, d, D}), P2B = view(P2.PB, {xki, d, D, c2});
+    Tn P3T = view(P3.PT, {c3, xib, D, P}), P3B = view(P3.PB, {xib, D, P, c3});
+
+    // ---- enlarged corners with the stage-1 bra projections on both legs
+    Tn Etop = ctr("xy,xkc->ykc", C1, K);
+    Tn E = ctr("ykc,ylg->kclg", Etop, K);
+    E = ctr("kclg,plkrn->cgprn", E, A);
+    E = ctr("cgprn,cie->egiprn", E, I);
+    E = ctr("egiprn,gmj->eijmprn", E, I);
+    E = ctr("eijmprn,pqmist->ejqrnst", E, O);
+    E = ctr("ejqrnst,ebf->fbjqrnst", E, Bt);
+    E = ctr("fbjqrnst,jwv->fbwvqrnst", E, Bt);
+    E = ctr("fbwvqrnst,qwbhe->fvrnsthe", E, A);
+    E = ctr("fvrnsthe,cve->fcrnsth", E, P1T);
+    Tn C1p = ctr("fcrnsth,Xfh->cntXrs", E, P1T);       // [c_d, Ad, Od, c_r, Ar, Or]
+    Tn F = ctr("xy,wvx->wvy", C4, Bt);
+    F = ctr("wvy,yac->wvac", F, Rk);
+    F = ctr("wvac,jmw->jmvac", F, I);
+    F = ctr("jmvac,cod->jmvaod", F, Ri);
+    F = ctr("jmvaod,pqmuro->jvadpqur", F, O);
+    F = ctr("jvadpqur,klj->klvadpqur", F, K);
+    F = ctr("klvadpqur,plzsa->kvdqurzs", F, A);
+    F = ctr("kvdqurzs,dbe->kvbequrzs", F, Rb);
+    F = ctr("kvbequrzs,qvtwb->keurzstw", F, A);         // [a0, s3, Ou, Or, Au, Ar, Bu, Br]
+    F = ctr("keurzstw,ktc->ceurzsw", F, P1B);
+    Tn C4p = ctr("ceurzsw,esX->czuXwr", F, P1B);       // [c_u, Au, Ou, c_r', Br, Or]
+
+    // ---- stage 2: half P4 from the two corners
+    const int64_t n4 = c1 * D * d;
+    Tn rB4 = perm(C4p, "cauXbo->Xbocau");
+    Projector P4 = projector(view(C1p, {n4, n4}), view(rB4, {n4, n4}), chi);
+
+    // ---- stage 2: P5 (ki) and P6 (ib) from the two-column block
+    Tn L = ctr("ykibf,ylg->kibflg", TRpre, K);
+    Tn ULraw = ctr("kibflg,plkrn->ibfgpnr", L, A);      // [Ou, Bu, s3, tkb, p, Ad, Ar]
+    Tn UL5 = ctr("ibfgpnr,cgib->cfpnr", ULraw, P2T);   // [c2L, s3, p, Ad, Ar]
+    Tn J = ctr("fkc,cie->fkie", K, I);
+    J = ctr("fkie,ebh->fkibh", J, Bt);
+    J = ctr("fkibh,hz->fkibz", J, C4);
+    J = ctr("fkibz,zrg->fkibrg", J, Rk);
+    Tn URraw = ctr("fkibrg,plkrn->fibgpln", J, A);      // [s3, Ou, Bu, rkb, p, Al, Ad]
+    Tn UR5 = ctr("fibgpln,gnpc->fiblc", URraw, P3B);   // P2^R_T = P3_B: [s3, Ou2, Bu2, Al2, c2R]
+    Tn rT5 = ctr("cfpnr,fibrd->cnpibd", UL5, UR5);      // [c2L, Ad1, p1, Ou2, Bu2, c2R]
+    Tn H6 = ctr("ibfgpnr,gmj->ibfjmpnr", ULraw, I);
+    H6 = ctr("ibfjmpnr,pqmist->bfjqnrst", H6, O);
+    Tn UL6 = ctr("bfjqnrst,cjbq->cfnrst", H6, P3T);    // [c3L, s3, Ad1, Ar1, Or1, Od1]
+    Tn K6 = ctr("fibgpln,gsh->fibpslnh", URraw, Ri);
+    K6 = ctr("fibpslnh,pqmist->fblnhqmt", K6, O);
+    Tn UR6 = ctr("fblnhqmt,htnc->fblqmc", K6, P2B);    // P3^R_T = P2_B: [s3, Bu2, Al2, q2, Ol2, c3R]
+    Tn rT6 = ctr("cfnrst,fbrqsd->cntbqd", UL6, UR6);    // [c3L, Ad1, Od1, Bu2, q2, c3R]
+    Tn rB5 = perm(rT6, "gfebca->efgabc");               // rotation image of rho_T6
+    Tn rB6 = perm(rT5, "gefcba->efgabc");               // rotation image of rho_T5
+    Projector P5 = projector(view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P}), chi);
+    Projector P6 = projector(view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d}), chi);
+    const int64_t k4 = P4.k, k5 = P5.k, k6 = P6.k;
+    Tn P4T = view(P4.PT, {k4, c1, D, d}), P4B = view(P4.PB, {c1, D, d, k4});
+    Tn P5T = view(P5.PT, {k5, c2, D, P}), P5B = view(P5.PB, {c2, D, P, k5});
+    Tn P6T = view(P6.PT, {k6, c3, D, d}), P6B = view(P6.PB, {c3, D, d, k6});
+
+    // ---- two-stage projectors of the three bonds
+    Tn PbkT = ctr("ncao,cxb->nxaob", P4T, P1T);         // [n, chi, A, O, B]
+    Tn PbkB = ctr("xbc,caon->xaobn", P1B, P4B);         // [chi, A, O, B, n]
+    Tn PkiT = ctr("ncap,cxob->nxapob", P5T, P2T);       // [n, chi, A, p, O, B]
+    Tn PkiB = ctr("xobc,capn->xapobn", P2B, P5B);       // [chi, A, p, O, B, n]
+    Tn PibT = ctr("ncao,cxbq->nxaoqb", P6T, P3T);       // [n, chi, A, O, q, B]
+    Tn PibB = ctr("xbqc,caon->xaoqbn", P3B, P6B);       // [chi, A, O, q, B, n]
+
+    // ---- renormalised left edge (row-wise absorption, both neighbouring bonds)
+    Tn X = ctr("xuosn,xlb->nuoslb", PbkB, K);
+    X = ctr("nuoslb,plumd->nosbpmd", X, A);
+    Tn Tk_n = ctr("nosbpmd,kbdpos->nmk", X, PkiT);
+    X = ctr("xapusn,xlb->napuslb", PkiB, I);
+    X = ctr("napuslb,pqlumt->nasbmtq", X, O);
+    Tn Ti_n = ctr("nasbmtq,kbatqs->nmk", X, PibT);
+    X = ctr("xaoqun,xlb->naoqulb", PibB, Bt);
+    X = ctr("naoqulb,qlumt->naobmt", X, A);
+    Tn Tb_n = ctr("naobmt,kbaot->nmk", X, PbkT);
+    // ---- corners: second-stage projectors on the stage-1 renormalised corners
+    Tn W1 = ctr("cdfqre,Xqre->cdfX", C1p, P4T);
+    Tn C1_n = ctr("cdfX,Ycdf->XY", W1, P4T);
+    Tn W4 = ctr("cwhXyi,cwhx->xXyi", C4p, P4B);
+    Tn C4_n = ctr("xXyi,Xyiz->xz", W4, P4B);
+    ctmk::symmetrize(st, C1_n.p, (int)k4);
+    ctmk::symmetrize(st, C4_n.p, (int)k4);
+    normalize(C1_n);
+    normalize(C4_n);
+    normalize(Tk_n);
+    normalize(Ti_n);
+    normalize(Tb_n);
+
+    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2
+    Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
+    Tn R = ctr("ab,bc->ac", R1, R1);
+    ctmk::trace(st, R.p, (int)k4, N.sc + 7);
+    Tn Uj, Vj, Sj;
+    jacobi(R, k4, k4, Uj, Vj, Sj);
+    ctmk::spectrum_delta(st, Sj.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
+
+    // ---- store
+    N.xbk = k4;
+    N.xki = k5;
+    N.xib = k6;
+    ctmk::copy(st, C1_n.p, N.C1, C1_n.n());
+    ctmk::copy(st, C4_n.p, N.C4, C4_n.n());
+    ctmk::copy(st, Tk_n.p, N.Tk, Tk_n.n());
+    ctmk::copy(st, Ti_n.p, N.Ti, Ti_n.n());
+    ctmk::copy(st, Tb_n.p, N.Tb, Tb_n.n());
+    ws.release(mk);
+}
+
+// n1, n2h, n2v, n0 into N.sc[0..3], ln kappa into N.sc[4], flag N.sc[5];
+// with_env: also the bra environment into N.E and its overlap with A in N.sc[6]
+void ctm_ctx::values(Net& N, double* /*unused*/, bool with_env)
+{
+    const int64_t D = this->D, d = N.d, P = 2;
+    const Arena::Mark mk = ws.mark();
+    Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
+    Tn K = make_tn(N.Tk, {N.xbk, D, N.xki});
+    Tn I = make_tn(N.Ti, {N.xki, d, N.xib});
+    Tn Bt = make_tn(N.Tb, {N.xib, D, N.xbk});
+    Tn A = make_tn(this->A, {P, D, D, D, D});
+    Tn O = make_tn(N.O, {P, P, d, d, d, d});
+    Tn Rk = perm(Bt, "bma->amb"), Ri = perm(I, "bma->amb"), Rb = perm(K, "bma->amb");
+    Tn H = ctr("xy,xkc->ykc", C1, K);
+    H = ctr("ykc,cie->ykie", H, I);
+    H = ctr("ykie,ebf->ykibf", H, Bt);
+    Tn TR = ctr("ykibf,fz->ykibz", H, C4);              // [y1, Au, Ou, Bu, y2]
+    Tn BR = perm(TR, "fecba->abcef");                   // [x4, Ad, Od, Bd, x3] (rotation image)
+    Tn U = ctr("ykibz,ylg->glkibz", TR, K);
+    U = ctr("glkibz,plkrn->gpnribz", U, A);
+    U = ctr("gpnribz,zrh->gpnibh", U, Rk);
+    U = ctr("gpnibh,gmj->jmpnibh", U, I);
+    U = ctr("jmpnibh,pqmist->jqtsnbh", U, O);
+    Tn upib = ctr("jqtsnbh,hsk->jqtnbk", U, Ri);
+    U = ctr("jqtnbk,jwv->vwqtnbk", upib, Bt);
+    U = ctr("vwqtnbk,qwbse->vsetnk", U, A);
+    Tn upbk = ctr("vsetnk,ksz->vetnz", U, Rb);
+    Tn s1 = ctr("vetnz,vntez->", upbk, BR);
+    Tn s2h = ctr("yaobz,yaobz->", TR, BR);
+    Tn X = ctr("xy,xz->yz", C1, C4);
+    X = ctr("yz,yma->zma", X, K);
+    X = ctr("zma,zmb->ab", X, Rk);
+    X = ctr("ab,amc->bmc", X, I);
+    X = ctr("bmc,bme->ce", X, Ri);
+    X = ctr("ce,cmf->emf", X, Bt);
+    X = ctr("emf,emg->fg", X, Rb);
+    X = ctr("fg,fh->gh", X, C4);
+    Tn s2v = ctr("gh,gh->", X, C1);
+    Tn R1 = ctr("ab,bc->ac", C1, C4);
+    Tn s0 = ctr("ab,ba->", R1, R1);
+    ctmk::copy(st, s1.p, N.sc + 0, 1);
+    ctmk::copy(st, s2h.p, N.sc + 1, 1);
+    ctmk::copy(st, s2v.p, N.sc + 2, 1);
+    ctmk::copy(st, s0.p, N.sc + 3, 1);
+    ctmk::log_kappa(st, N.sc, N.sc + 4);
+    if (with_env) {
+        Tn G = ctr("jqtnbk,jwv->qtnbwvk", upib, Bt);
+        G = ctr("qtnbwvk,ksz->qtnbwvsz", G, Rb);
+        Tn Env = ctr("qtnbwvsz,vntez->qwbse", G, BR);   // [q, Bl, Bu, Br, Bd]
+        ctmk::copy(st, Env.p, N.E, Env.n());
+        ctmk::dot(st, Env.p, this->A, Env.n(), N.sc + 6, part, 0);
+    }
+    ws.release(mk);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+static std::string g_init_err = "no error";
+
+template <class F>
+static ctm_status guarded(ctm_ctx* c, F&& f)
+{
+    try {
+        f();
+        return CTM_OK;
+    } catch (const CtmError& e) {
+        if (c) c->err = e.what();
+        return (ctm_status)e.code;
+    } catch (const std::exception& e) {
+        if (c) c->err = e.what();
+        return CTM_EDEVICE;
+    }
+}
+
+static void init_net(ctm_ctx* c, Net& N, int d)
+{
+    N.d = d;
+    const int64_t x = c->xmax, D = c->D;
+    N.O = c->keep(4 * (int64_t)d * d * d * d);
+    N.C1 = c->keep(x * x);
+    N.C4 = c->keep(x * x);
+    N.Tk = c->keep(x * x * D);
+    N.Ti = c->keep(x * x * d);
+    N.Tb = c->keep(x * x * D);
+    N.s_old = c->keep(x);
+    N.n_old = (int*)c->keep(1);
+    N.delta = c->keep(1);
+    N.sc = c->keep(16);
+    N.E = c->keep(2 * D * D * D * D);
+    N.sv = c->keep(x);
+}
+
+static void reset_env(ctm_ctx* c, Net& N)
+{
+    const int64_t D = c->D, d = N.d;
+    N.xbk = N.xki = N.xib = 1;
+    ctmk::fill(c->st, N.C1, 1, 1.0);
+    ctmk::fill(c->st, N.C4, 1, 1.0);
+    ctmk::fill(c->st, N.Tk, D, 1.0 / std::sqrt((double)D));
+    ctmk::fill(c->st, N.Ti, d, 1.0 / std::sqrt((double)d));
+    ctmk::fill(c->st, N.Tb, D, 1.0 / std::sqrt((double)D));
+    ctmk::fill(c->st, N.s_old, 1, 1.0);
+    int one = 1;
+    HIPCHK(hipMemcpyAsync(N.n_old, &one, sizeof(int), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+}
+
+static void load_tensor(ctm_ctx* c, double beta, const double* A)
+{
+    const int64_t n = 2 * (int64_t)c->D * c->D * c->D * c->D;
+    double* raw = c->ws.alloc(n);
+    const bool dev = (c->cfg.flags & CTM_FLAG_DEVICE_PTRS) != 0;
+    HIPCHK(hipMemcpyAsync(raw, A, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
+    ctmk::d4_project(c->st, raw, c->A, c->D);
+    int* flag = (int*)c->ws.alloc(1);
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), c->st));
+    ctmk::finite_check(c->st, c->A, n, flag);
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    ctmk::ising_pepo(c->st, c->net[0].O, beta);
+    ctmk::identity_pepo(c->st, c->net[1].O);
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->ws.release({0, 0});
+    if (hflag) throw CtmError(CTM_ENUMERIC, "A contains NaN or Inf");
+    c->beta = beta;
+}
+
+extern "C" {
+
+int ctm_abi_version(void) { return CTM_ABI_VERSION; }
+
+const char* ctm_status_string(int s)
+{
+    switch (s) {
+    case CTM_OK: return "ok";
+    case CTM_EINVAL: return "invalid argument";
+    case CTM_ENOMEM: return "out of device memory";
+    case CTM_EDEVICE: return "HIP device error";
+    case CTM_ENOCONV: return "not converged";
+    case CTM_ENUMERIC: return "numerical failure";
+    case CTM_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char* ctm_last_error(const ctm_ctx* c)
+{
+    if (!c) return g_init_err.c_str();
+    return c->err.c_str();
+}
+
+ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* hip_stream, ctm_ctx** out)
+{
+    if (out) *out = nullptr;
+    if (!cfg || !A || !out) { g_init_err = "NULL argument"; return CTM_EINVAL; }
+    if (!(beta > 0.0) || !std::isfinite(beta)) { g_init_err = "beta must be > 0"; return CTM_EINVAL; }
+    if (cfg->D < 1 || cfg->D > 8) { g_init_err = "D must be in [1, 8]"; return CTM_EINVAL; }
+    if (cfg->chi < 1 || cfg->chi > 512) { g_init_err = "chi must be in [1, 512]"; return CTM_EINVAL; }
+    if (cfg->tol < 0.0 || cfg->max_iter < 0) { g_init_err = "tol and max_iter must be >= 0"; return CTM_EINVAL; }
+    if (cfg->precision != CTM_FP64) { g_init_err = "only CTM_FP64 is implemented"; return CTM_EINVAL; }
+    ctm_ctx* c = new (std::nothrow) ctm_ctx();
+    if (!c) { g_init_err = "host allocation failed"; return CTM_ENOMEM; }
+    ctm_status s = guarded(c, [&] {
+        c->cfg = *cfg;
+        c->D = cfg->D;
+        c->chi = cfg->chi;
+        c->xmax = std::max(cfg->chi, 2 * 2 * cfg->D * cfg->D);
+        c->st = (hipStream_t)hip_stream;
+        HIPCHK(hipGetDevice(&c->device));
+        c->A = c->keep(2 * (int64_t)c->D * c->D * c->D * c->D);
+        c->part = c->keep(ctmk::kRedBlocks);
+        c->scal = c->keep(16);
+        c->icount = (int*)c->keep(1);
+        init_net(c, c->net[0], 2);
+        init_net(c, c->net[1], 1);
+        load_tensor(c, beta, A);
+        reset_env(c, c->net[0]);
+        reset_env(c, c->net[1]);
+    });
+    if (s != CTM_OK) {
+        g_init_err = c->err;
+        ctm_destroy(c);
+        return s;
+    }
+    *out = c;
+    return CTM_OK;
+}
+
+ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_delta)
+{
+    if (!c) return CTM_EINVAL;
+    int done = 0;
+    double dl = 0.0;
+    bool conv = false;
+    ctm_status s = guarded(c, [&] {
+        const bool until = n_iter <= 0;
+        const int budget = until ? std::max(0, c->cfg.max_iter - c->iters) : n_iter;
+        for (int it = 0; it < budget; ++it) {
+            // the first move from the product boundary never truncates
+            const int64_t chi = (c->iters == 0) ? (int64_t)INT_MAX : (int64_t)c->chi;
+            c->step(c->net[0], chi);
+            c->step(c->net[1], chi);
+            ++c->iters;
+            ++done;
+            if (until || it == budget - 1) {
+                double h[2];
+                HIPCHK(hipMemcpyAsync(&h[0], c->net[0].delta, sizeof(double), hipMemcpyDeviceToHost, c->st));
+                HIPCHK(hipMemcpyAsync(&h[1], c->net[1].delta, sizeof(double), hipMemcpyDeviceToHost, c->st));
+                HIPCHK(hipStreamSynchronize(c->st));
+                dl = std::max(h[0], h[1]);
+                if (!std::isfinite(dl)) throw CtmError(CTM_ENUMERIC, "non-finite spectrum");
+                if (until && c->iters > 1 && dl < c->cfg.tol) { conv = true; break; }
+            }
+        }
+        HIPCHK(hipStreamSynchronize(c->st));
+    });
+    if (iters_done) *iters_done = done;
+    if (last_delta) *last_delta = dl;
+    if (s == CTM_OK && n_iter <= 0 && !conv) {
+        c->err = "max_iter reached before tol";
+        return CTM_ENOCONV;
+    }
+    return s;
+}
+
+ctm_status ctm_free_energy(ctm_ctx* c, double* f, double* lk3, double* lk2)
+{
+    if (!c) return CTM_EINVAL;
+    if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
+    double h[6] = {0, 0, 0, 0, 0, 0};
+    ctm_status s = guarded(c, [&] {
+        c->values(c->net[0], nullptr, false);
+        c->values(c->net[1], nullptr, false);
+        ctmk::free_energy(c->st, c->net[0].sc + 4, c->net[1].sc + 4, c->beta, c->scal);
+        HIPCHK(hipMemcpyAsync(&h[0], c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(&h[1], c->net[0].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(&h[3], c->net[1].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        if (h[2] != 0.0 || h[4] != 0.0 || !std::isfinite(h[0]))
+            throw CtmError(CTM_ENUMERIC, "non-positive or non-finite network value");
+    });
+    if (s == CTM_OK) {
+        if (f) *f = h[0];
+        if (lk3) *lk3 = h[1];
+        if (lk2) *lk2 = h[3];
+    }
+    return s;
+}
+
+ctm_status ctm_grad(ctm_ctx* c, double* g)
+{
+    if (!c || !g) return CTM_EINVAL;
+    if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
+    return guarded(c, [&] {
+        c->values(c->net[0], nullptr, true);
+        c->values(c->net[1], nullptr, true);
+        const int n = 2 * c->D * c->D * c->D * c->D;
+        const Arena::Mark mk = c->ws.mark();
+        double* graw = c->ws.alloc(n);
+        double* gsym = c->ws.alloc(n);
+        ctmk::grad_combine(c->st, c->net[0].E, c->net[0].sc + 6, c->net[1].E, c->net[1].sc + 6,
+                           c->beta, graw, n);
+        ctmk::d4_project(c->st, graw, gsym, c->D);
+        const bool dev = (c->cfg.flags & CTM_FLAG_DEVICE_PTRS) != 0;
+        HIPCHK(hipMemcpyAsync(g, gsym, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        c->ws.release(mk);
+    });
+}
+
+ctm_status ctm_corner_spectrum(ctm_ctx* c, int which, double* s, int cap, int* n)
+{
+    if (!c || !s || !n || (which != 2 && which != 3)) return CTM_EINVAL;
+    if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
+    return guarded(c, [&] {
+        Net& N = c->net[which == 3 ? 0 : 1];
+        int cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, N.n_old, sizeof(int), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        cnt = std::min(cnt, cap);
+        HIPCHK(hipMemcpyAsync(s, N.s_old, cnt * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        *n = cnt;
+    });
+}
+
+ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A)
+{
+    if (!c || !A) return CTM_EINVAL;
+    if (!(beta > 0.0)) { c->err = "beta must be > 0"; return CTM_EINVAL; }
+    return guarded(c, [&] { load_tensor(c, beta, A); });
+}
+
+ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes)
+{
+    if (!c) return CTM_EINVAL;
+    if (total_iters) *total_iters = c->iters;
+    if (device_bytes) {
+        long long b = (long long)c->ws.bytes_held;
+        const int64_t x = c->xmax, D = c->D;
+        b += (long long)sizeof(double) * (2 * (2 * x * x + 2 * x * x * D + x * x * 2) + 2 * D * D * D * D);
+        *device_bytes = b;
+    }
+    return CTM_OK;
+}
+
+void ctm_destroy(ctm_ctx* c)
+{
+    if (!c) return;
+    if (c->st || true) (void)hipStreamSynchronize(c->st);
+    c->ws.free_all();
+    for (void* p : c->owned) (void)hipFree(p);
+    delete c;
+}
+
+}  // extern "C"

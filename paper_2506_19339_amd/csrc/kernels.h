@@ -1,0 +1,58 @@
+// Internal launcher declarations of the split-CTMRG device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ctmk {
+
+struct PermDesc {
+    int rank;
+    int64_t od[12];  // output dims (row-major)
+    int64_t is[12];  // input stride of each output dim
+};
+
+struct JacobiJob {
+    double* X;  // m x n column-major input (destroyed)
+    double* W;  // n x n workspace
+    double* U;  // m x n column-major output
+    double* V;  // n x n column-major output
+    double* S;  // n singular values, descending
+    int m, n;
+};
+
+constexpr int kMaxJacobiBatch = 16;
+struct JacobiBatch {            // passed by value as a kernel argument
+    JacobiJob job[kMaxJacobiBatch];
+    int n;
+};
+
+void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+              const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
+              double beta, double* C, int64_t ldc, int64_t sC, int batch);
+void permute(hipStream_t s, const double* in, double* out, const PermDesc& pd, int64_t n);
+void dot(hipStream_t s, const double* x, const double* y, int64_t n, double* out, double* part, int mode);
+void scale_inv(hipStream_t s, double* x, int64_t n, const double* dev_scalar);
+void fill(hipStream_t s, double* x, int64_t n, double v);
+void copy(hipStream_t s, const double* a, double* b, int64_t n);
+void eye(hipStream_t s, double* x, int n);
+void symmetrize(hipStream_t s, double* x, int n);
+void scale_lines(hipStream_t s, double* x, int R, int C, const double* f, int mode);
+void inv_sqrt_cut(hipStream_t s, const double* S, double* f, int n, double cutoff);
+void count_above(hipStream_t s, const double* S, int n, double cutoff, int* out);
+void randn(hipStream_t s, double* x, int64_t n, uint64_t seed);
+void d4_project(hipStream_t s, const double* A, double* out, int D);
+void ising_pepo(hipStream_t s, double* O, double beta);
+void identity_pepo(hipStream_t s, double* O);
+void log_kappa(hipStream_t s, const double* sc, double* out);
+void free_energy(hipStream_t s, const double* lk3, const double* lk2, double beta, double* f);
+void grad_combine(hipStream_t s, const double* E3, const double* n13, const double* E2,
+                  const double* n12, double beta, double* g, int n);
+void spectrum_delta(hipStream_t s, double* sv, int n, const double* trace, double* s_old,
+                    int* n_old, double* delta);
+void trace(hipStream_t s, const double* X, int n, double* out);
+void finite_check(hipStream_t s, const double* x, int64_t n, int* flag);
+void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps);
+
+constexpr int kRedBlocks = 256;  // partial-sum slots needed by dot()
+
+}  // namespace ctmk

@@ -1,0 +1,112 @@
+"""Parity of the HIP split-CTMRG path with the FP64 CPU oracle (same wiring,
+same truncation rule), through the C ABI.
+
+Tolerances (FP64 on both sides; the oracle uses LAPACK SVDs, the GPU its own
+Jacobi / subspace SVD): after the iteration has converged the two agree to
+rounding, amplified by the projectors' S^-1/2; we require 1e-10 relative on f,
+1e-8 relative (l2) on g and 1e-10 absolute on the normalised spectrum.
+"""
+import numpy as np
+import pytest
+
+from oracle import model, split
+from paper_2506_19339_amd import ctm
+from synth_inputs import WORKLOADS, raw_peps
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_run(beta, A, chi, n_iter, cutoff=1e-12):
+    As = model.d4_symmetrize(A)
+    O3, O2 = model.pepo_O(beta), model.identity_pepo()
+    e3, _, _, _ = split.run(As, O3, chi, n_iter, cutoff=cutoff)
+    e2, _, _, _ = split.run(As, O2, chi, n_iter, cutoff=cutoff)
+    l3, _ = split.log_kappa(e3, As, O3)
+    l2, _ = split.log_kappa(e2, As, O2)
+    g = split.gradient(beta, As, dict(env3=e3, env2=e2))
+    return -(l3 - l2) / beta, l3, l2, g, split.corner_spectrum(e3), split.corner_spectrum(e2)
+
+
+def gpu_run(beta, A, chi, n_iter):
+    with ctm.SplitCTM(beta, A, chi) as c:
+        done, _, _ = c.iterate(n_iter)
+        assert done == n_iter
+        f, l3, l2 = c.free_energy()
+        return f, l3, l2, c.grad(), c.spectrum(3), c.spectrum(2)
+
+
+def compare(got, ref):
+    f, l3, l2, g, s3, s2 = got
+    fo, l3o, l2o, go, s3o, s2o = ref
+    assert abs(f - fo) <= 1e-10 * abs(fo), (f, fo)
+    assert abs(l3 - l3o) <= 1e-10 * abs(l3o) and abs(l2 - l2o) <= 1e-10 * abs(l2o)
+    assert np.linalg.norm(g - go) <= 1e-8 * np.linalg.norm(go)
+    for s, so in ((s3, s3o), (s2, s2o)):
+        n = max(len(s), len(so))
+        a, b = np.zeros(n), np.zeros(n)
+        a[: len(s)], b[: len(so)] = s, so
+        assert np.max(np.abs(a - b)) <= 1e-10
+
+
+def test_d2_chi16_forty_iterations():
+    """The plain FP64 workload: beta = 0.20, D = 2, chi = 16, 40 iterations."""
+    w = WORKLOADS["d2_chi16"]
+    A = raw_peps(w["D"], w["seed"])
+    compare(gpu_run(w["beta"], A, w["chi"], w["max_iter"]),
+            oracle_run(w["beta"], A, w["chi"], w["max_iter"]))
+
+
+def test_first_move_is_exact_growth():
+    """One iteration = untruncated growth from the product boundary."""
+    A = raw_peps(2, 0)
+    compare(gpu_run(0.2, A, 16, 1), oracle_run(0.2, A, 16, 1))
+
+
+@pytest.mark.parametrize("D,chi,n_iter,seed", [(3, 20, 30, 1), (2, 7, 40, 4)])
+def test_other_shapes(D, chi, n_iter, seed):
+    """Ragged chi (not a multiple of the GEMM tile) and D = 3."""
+    A = raw_peps(D, seed)
+    compare(gpu_run(0.22, A, chi, n_iter), oracle_run(0.22, A, chi, n_iter))
+
+
+def test_product_state_reduces_to_2d_ising():
+    from oracle import exact
+    A = model.embed_product_state(2, +1)
+    with ctm.SplitCTM(0.2, A, 16) as c:
+        c.iterate(60)
+        f, _, l2 = c.free_energy()
+    assert abs(f - exact.product_state_f(0.2, +1)) < 1e-8
+    assert abs(l2) < 1e-12
+
+
+def test_error_paths():
+    A = raw_peps(2, 0)
+    with ctm.SplitCTM(0.2, A, 8, max_iter=3, tol=1e-30) as c:
+        with pytest.raises(ctm.CtmError) as e:
+            c.free_energy()
+        assert e.value.status == 6                 # CTM_ESTATE before any iteration
+        done, delta, converged = c.iterate(0)      # until tol: max_iter reached
+        assert done == 3 and not converged
+        f, _, _ = c.free_energy()                  # values stay readable
+        assert np.isfinite(f)
+    bad = A.copy()
+    bad[0, 0, 0, 0, 0] = np.nan
+    with pytest.raises(ctm.CtmError) as e:
+        ctm.SplitCTM(0.2, bad, 8)
+    assert e.value.status == 5                     # CTM_ENUMERIC
+    with pytest.raises(ctm.CtmError):
+        ctm.SplitCTM(0.0, A, 8)
+
+
+def test_warm_restart_and_determinism():
+    A = raw_peps(2, 0)
+    r1 = gpu_run(0.2, A, 12, 20)
+    r2 = gpu_run(0.2, A, 12, 20)
+    assert r1[0] == r2[0] and np.array_equal(r1[3], r2[3])   # bitwise repeatable
+    with ctm.SplitCTM(0.2, A, 12) as c:
+        c.iterate(30)
+        f1, _, _ = c.free_energy()
+        c.reset_tensor(0.2, A)
+        c.iterate(5)
+        f2, _, _ = c.free_energy()
+    assert abs(f1 - f2) < 1e-10 * abs(f1)
