@@ -1,0 +1,175 @@
+"""Benchmark: f + grad evaluations per second of the split-CTMRG HIP path.
+
+One step = one complete evaluation of the hot path for one PEPS tensor:
+ctm_init (PEPO, D4 projection, product-boundary environments of both networks),
+ctm_iterate until the corner-spectrum change drops below tol (or max_iter),
+ctm_free_energy and ctm_grad.  The PEPS tensor is resident in HBM before the
+timed region starts (a float64 torch tensor on cuda:0, passed by pointer).
+
+Prints one JSON line (rank 0, one GPU).  Besides the throughput it reports
+  roofline     the kernel class with the largest share of device time in one
+               profiled evaluation (HIP events on the library's stream around
+               every launch), its algorithmic rate and the matching peak;
+  cpu_baseline the FP64 NumPy oracle (the same split-CTMRG steps) timed on the
+               host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from synth_inputs import WORKLOADS, workload_peps  # noqa: E402
+
+PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
+
+
+def gpu_eval(ctm, torch, w, A, g, stream, profile=False):
+    c = ctm.SplitCTM(w["beta"], A, w["chi"], max_iter=w["max_iter"], tol=w["tol"],
+                     stream=stream, profile=profile)
+    done, delta, conv = c.iterate(0)
+    f, lk3, lk2 = c.free_energy()
+    c.grad(g)
+    return c, dict(iters=done, delta=delta, converged=conv, f=f)
+
+
+def cpu_baseline(name, sample_iters):
+    """Oracle (FP64 NumPy, same wiring) on a bounded sample: the first
+    `sample_iters` iterations of both networks of the workload, then the
+    per-evaluation time is extrapolated with the GPU's iteration count."""
+    from oracle import model, split
+    w = WORKLOADS[name]
+    A = model.d4_symmetrize(workload_peps(name))
+    t_net = []
+    for O in (model.pepo_O(w["beta"]), model.identity_pepo()):
+        env = split.init_env(A.shape[1], O.shape[2])
+        env, _ = split.step(env, A, O, split.GROW_CHI)
+        times = []
+        for _ in range(sample_iters):
+            t0 = time.perf_counter()
+            env, _ = split.step(env, A, O, w["chi"])
+            times.append(time.perf_counter() - t0)
+        t_net.append(float(np.mean(times)))
+    return t_net
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="d5_chi100")
+    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile-pass", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(independent evaluations would shard one per GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_19339_amd import ctm
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    A = torch.from_numpy(workload_peps(args.workload)).to(dev)
+    g = torch.empty_like(A)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        t1 = time.perf_counter()
+        c, info = gpu_eval(ctm, torch, w, A, g, sp)
+        c.close()
+        print("warmup %d: %d iterations, %.2f s, f = %.12f" % (i, info["iters"], time.perf_counter() - t1,
+                                                              info["f"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    iters = []
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        c, info = gpu_eval(ctm, torch, w, A, g, sp)
+        iters.append(info["iters"])
+        c.close()
+        print("step %d: %d iterations" % (i, info["iters"]), file=sys.stderr, flush=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    elapsed = max(ms / 1e3, wall)
+    evals_per_s = args.steps / elapsed
+    iter_per_s = sum(iters) / elapsed
+
+    roofline = None
+    if not args.no_profile_pass:
+        print("profile pass", file=sys.stderr, flush=True)
+        c, pinfo = gpu_eval(ctm, torch, w, A, g, sp, profile=True)
+        stats = {k: c.kernel_stats(k) for k in (0, 1)}
+        c.close()
+        gl, gms, gfl = stats[0]
+        jl, jms, _ = stats[1]
+        if gms >= jms:
+            ach = gfl / (gms / 1e3) / 1e12
+            roofline = dict(kernel="gemm_f64_kernel (v_mfma_f64_16x16x4)", bound="mfma",
+                            achieved=ach, peak=PEAK_FP64_MFMA_TFLOPS, unit="TFLOP/s",
+                            frac=ach / PEAK_FP64_MFMA_TFLOPS, traffic=None,
+                            launches=gl, avg_launch_us=1e3 * gms / max(gl, 1),
+                            share_of_kernel_time=gms / (gms + jms))
+        else:
+            roofline = dict(kernel="jacobi_svd_kernel", bound="alu", achieved=None,
+                            peak=PEAK_FP64_VECTOR_TFLOPS, unit="TFLOP/s", frac=None,
+                            traffic=None, launches=jl, avg_launch_us=1e3 * jms / max(jl, 1),
+                            share_of_kernel_time=jms / (gms + jms),
+                            gemm_achieved_tflops=gfl / max(gms, 1e-9) / 1e9)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("cpu baseline (oracle)", file=sys.stderr, flush=True)
+        t3, t2 = cpu_baseline(args.workload, args.cpu_sample_iters)
+        n_it = float(np.mean(iters))
+        t_eval = n_it * (t3 + t2)
+        cpu = dict(value=1.0 / t_eval, unit="evals/s", cores=len(os.sched_getaffinity(0)),
+                   kind="oracle",
+                   sample="%d steady-state split-CTMRG iterations per network of the same "
+                          "workload (after the growth move), %.2f s triple + %.2f s double per "
+                          "iteration, extrapolated to %.1f iterations per evaluation"
+                          % (args.cpu_sample_iters, t3, t2, n_it))
+
+    out = {
+        "metric": "f+grad evals/s (D=5, chi=100, beta=0.22, FP64)",
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: beta=%g D=%d chi=%d tol=%g max_iter=%d, A = D4-projected "
+                               "N(0,1) tensor (seed %d), f + grad per step"
+                               % (args.workload, w["beta"], w["D"], w["chi"], w["tol"],
+                                  w["max_iter"], w["seed"])},
+        "ctmrg_iter_per_s": iter_per_s,
+        "iters_per_eval": float(np.mean(iters)),
+        "f": info["f"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,6 +64,7 @@ typedef enum {
 } ctm_precision;
 
 #define CTM_FLAG_DEVICE_PTRS 1
+#define CTM_FLAG_PROFILE 2      /* record HIP events around GEMM / Jacobi launches */
 
 typedef struct {
     int D;              /* PEPS virtual bond dimension, 1 <= D <= 8               */
@@ -73,7 +74,7 @@ typedef struct {
     int precision;      /* ctm_precision of the bulk contractions                 */
     int flags;          /* CTM_FLAG_* bits                                        */
     int power_iters;    /* subspace iterations of the projector SVD (0: default)  */
-    double svd_cutoff;  /* relative singular-value cutoff (0: default 1e-12)      */
+    double svd_cutoff;  /* relative singular-value cutoff (0: default 1e-8)       */
 } ctm_config;
 
 /* Build a context: the PEPO O of the 3D Ising model at inverse temperature
@@ -115,6 +116,13 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A);
 
 /* Iterations done so far, and the device bytes the context holds. */
 ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes);
+
+/* Launch statistics of a context built with CTM_FLAG_PROFILE: which = 0 the
+ * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernel, 2 the Cholesky QR kernel.  launches, summed kernel time
+ * in ms (HIP events on the context stream around each launch) and algorithmic
+ * flops (2 M N K per GEMM; 0 for the factorisations).  Synchronises the stream.  Any output
+ * may be NULL.  CTM_ESTATE without CTM_FLAG_PROFILE. */
+ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops);
 
 /* Release a context.  NULL-safe. */
 void ctm_destroy(ctm_ctx* c);

@@ -33,6 +33,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -154,8 +155,24 @@ struct Net {
     double* sv = nullptr;            // spectrum buffer
 };
 
-constexpr int kJacobiExact = 256;   // exact Jacobi SVD up to this min(m, n)
+// per-kernel-class launch statistics (CTM_FLAG_PROFILE): HIP events on the
+// context stream around every launch, algorithmic flops per launch
+struct KStat {
+    int64_t launches = 0;
+    double flops = 0.0;
+    double ms = 0.0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+constexpr int kJacobiExact = 64;    // exact Jacobi SVD when min(m, n) <= this
+constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resident)
 constexpr int kOversample = 16;
+constexpr int64_t kCoreMax = 135;   // largest k x k factorisation held in LDS
+// relative pseudo-inverse cutoff of S^1/2: singular values of rho_B rho_T below
+// 1e-8 of the largest are dropped.  The subspace factorisation squares the
+// spectrum in its Gram steps, so 1e-8 is the smallest relative singular value
+// it resolves in FP64.
+constexpr double kDefaultCutoff = 1e-8;
 constexpr int kJacobiSweeps = 40;
 
 }  // namespace
@@ -175,6 +192,62 @@ struct ctm_ctx {
     Net net[2];                      // [0] triple, [1] double
     int iters = 0;
     uint64_t svd_calls = 0;
+    int64_t exact_min = kJacobiExact, exact_area = kJacobiExactArea;
+    bool profiling = false;
+    KStat kstat[3];                  // [0] GEMM (MFMA), [1] Jacobi SVD, [2] Cholesky QR
+    std::vector<hipEvent_t> ev_pool;
+
+    hipEvent_t ev_get()
+    {
+        if (ev_pool.empty()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = ev_pool.back();
+        ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t prof_begin()
+    {
+        if (!profiling) return nullptr;
+        hipEvent_t a = ev_get();
+        HIPCHK(hipEventRecord(a, st));
+        return a;
+    }
+    void prof_end(int cls, hipEvent_t a, double flops)
+    {
+        if (!profiling) return;
+        hipEvent_t b = ev_get();
+        HIPCHK(hipEventRecord(b, st));
+        kstat[cls].launches += 1;
+        kstat[cls].flops += flops;
+        kstat[cls].pending.push_back({a, b});
+    }
+    void prof_collect()
+    {
+        HIPCHK(hipStreamSynchronize(st));
+        for (auto& k : kstat) {
+            for (auto& pr : k.pending) {
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, pr.first, pr.second));
+                k.ms += t;
+                ev_pool.push_back(pr.first);
+                ev_pool.push_back(pr.second);
+            }
+            k.pending.clear();
+        }
+    }
+    void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+              int64_t sA, const double* B, int64_t ldb, int64_t sB, double* C, int64_t ldc,
+              int64_t sC, int64_t nb)
+    {
+        hipEvent_t e = prof_begin();
+        ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, (int)nb);
+        prof_end(0, e, 2.0 * (double)M * (double)N * (double)K * (double)nb);
+    }
+    struct Warm { double* V = nullptr; int64_t cap = 0, n = 0, k = 0; };
+    Warm warm[12];                   // per projector slot (network x P1..P6)
     std::string err;
 
     // ---------------- allocation helpers
@@ -313,9 +386,8 @@ struct ctm_ctx {
             ctmk::dot(st, Ao.p, Bo.p, K, C.p, part, 0);
         } else {
             REQUIRE(M < INT_MAX && N < INT_MAX && K < INT_MAX, "GEMM too large");
-            ctmk::gemm_f64(st, tA, tB, (int)M, (int)N, (int)K, 1.0,
-                           Ao.p, tA ? M : K, M * K, Bo.p, tB ? K : N, K * N,
-                           0.0, C.p, N, M * N, (int)nb);
+            gemm(tA, tB, M, N, K, Ao.p, tA ? M : K, M * K, Bo.p, tB ? K : N, K * N,
+                 C.p, N, M * N, nb);
         }
         if (lo == nat) return C;
         return permute_labels(C, nat, lo);
@@ -329,14 +401,13 @@ struct ctm_ctx {
         const int64_t K2 = tb ? B.d[1] : B.d[0], N = tb ? B.d[0] : B.d[1];
         REQUIRE(A.r == 2 && B.r == 2 && K == K2, "mm shapes");
         Tn C = tmp({M, N});
-        ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A.p, A.d[1], 0, B.p, B.d[1], 0,
-                       0.0, C.p, N, 0, 1);
+        gemm(ta, tb, M, N, K, A.p, A.d[1], 0, B.p, B.d[1], 0, C.p, N, 0, 1);
         return C;
     }
 
     // Jacobi SVD of X given as an m x n column-major matrix (n columns).
     // Returns U (m x n col-major), V (n x n col-major), S (n): X = U S V^T.
-    void jacobi(const Tn& Xcm, int64_t m, int64_t n, Tn& U, Tn& V, Tn& S)
+    void jacobi(const Tn& Xcm, int64_t m, int64_t n, Tn& U, Tn& V, Tn& S, bool want_v = true)
     {
         REQUIRE(n <= 1024, "Jacobi: too many columns");
         Tn X = tmp({n, m});
@@ -347,33 +418,44 @@ struct ctm_ctx {
         S = tmp({n});
         ctmk::JacobiBatch jb{};
         jb.n = 1;
-        jb.job[0] = ctmk::JacobiJob{X.p, W.p, U.p, V.p, S.p, (int)m, (int)n};
+        jb.job[0] = ctmk::JacobiJob{X.p, W.p, U.p, V.p, S.p, (int)m, (int)n, want_v ? 1 : 0};
+        hipEvent_t e = prof_begin();
         ctmk::jacobi_svd(st, jb, kJacobiSweeps);
+        prof_end(1, e, 0.0);
     }
 
-    // rows of Yt (k x L) -> orthonormal rows spanning the same space (SVQB):
-    // G = Yt Yt^T = V L V^T, Q^T = L^-1/2 V^T Yt, directions with tiny L dropped.
-    Tn svqb(const Tn& Yt)
+    // one shifted Cholesky QR pass on the rows of Yt (k x L): G = Yt Yt^T,
+    // T = L^-1 D with L L^T = D G D + shift I, D = diag(G)^-1/2; returns T Yt.
+    Tn cholqr_pass(const Tn& Yt)
     {
         const int64_t k = Yt.d[0];
         Tn G = mm(Yt, false, Yt, true);
-        Tn U, V, S;
-        jacobi(G, k, k, U, V, S);
-        Tn f = tmp({k});
-        ctmk::inv_sqrt_cut(st, S.p, f.p, (int)k, 1e-26);
-        // V col-major k x k == V^T row-major
-        Tn Vt = make_tn(V.p, {k, k});
-        Tn Q = mm(Vt, false, Yt, false);
-        ctmk::scale_lines(st, Q.p, (int)k, (int)Q.d[1], f.p, 0);
-        return Q;
+        Tn T = tmp({k, k});
+        Tn work = tmp({2 * k});
+        ctmk::CholBatch cb{};
+        cb.n = 1;
+        cb.job[0] = ctmk::CholJob{G.p, work.p, T.p, (int)k};
+        hipEvent_t e = prof_begin();
+        ctmk::cholqr(st, cb, 1e-14);
+        prof_end(2, e, 0.0);
+        return mm(T, false, Yt, false);
     }
 
-    // top-kk singular triplets of M (m x n row-major): UT (kk x m), S (kk), VT (kk x n)
-    void svd_topk(const Tn& M, int64_t kk, Tn& UT, Tn& S, Tn& VT)
+    // rows of Yt -> orthonormal rows spanning the same space (shifted
+    // Cholesky QR, twice).  Small directions are kept (the shift bounds their
+    // amplification) so that the power steps can refine them.
+    Tn orth(const Tn& Yt) { return cholqr_pass(cholqr_pass(Yt)); }
+
+    // top-kk singular triplets of M (m x n row-major): UT (kk x m), S (kk), VT (kk x n).
+    // min(m, n) <= kJacobiExact: exact one-sided Jacobi SVD.  Otherwise block
+    // subspace iteration on M^T M (k vectors, k >= kk + oversampling) started
+    // from counter-based normals, followed by a Rayleigh-Ritz step whose small
+    // core (Q^T M P) is factorised by Jacobi.
+    void svd_topk(const Tn& M, int64_t kk, int slot, Tn& UT, Tn& S, Tn& VT)
     {
         const int64_t m = M.d[0], n = M.d[1], mn = std::min(m, n);
         Tn U, V, Sv;
-        if (mn <= kJacobiExact) {
+        if (mn <= exact_min || m * n <= exact_area) {
             if (m <= n) {
                 // M row-major == M^T column-major (n rows, m columns)
                 jacobi(M, n, m, U, V, Sv);
@@ -389,20 +471,26 @@ struct ctm_ctx {
             S = make_tn(Sv.p, {kk});
             return;
         }
-        const int64_t k = std::min<int64_t>(kk + kOversample, mn);
+        // oversampling: near the cut the spectra of these environments are
+        // flat (sigma_{1.16 chi} / sigma_chi ~ 0.5), so the subspace extends
+        // to min(2 kk, 135) vectors (the largest core that stays in LDS) and
+        // six power steps resolve the kept directions to ~1e-10.  The bond
+        // gauge changes every iteration, so the previous subspace is no better
+        // a start than a random one.
+        const int64_t k = std::min<int64_t>(std::max<int64_t>(std::min<int64_t>(2 * kk, kCoreMax), kk + kOversample), mn);
         Tn Pt = tmp({k, n});
+        (void)slot;
         ctmk::randn(st, Pt.p, k * n, 0x5eedull + 7919ull * (++svd_calls));
-        const int q = cfg.power_iters > 0 ? cfg.power_iters : 4;
-        Pt = svqb(Pt);
+        const int q = cfg.power_iters > 0 ? cfg.power_iters : 6;
+        Pt = orth(Pt);
         for (int it = 0; it < q; ++it) {
             Tn Yt = mm(Pt, false, M, true);       // (M P)^T
-            Tn Qt = svqb(Yt);
+            Tn Qt = orth(Yt);
             Tn Zt = mm(Qt, false, M, false);      // (M^T Q)^T
-            Pt = svqb(Zt);
+            Pt = orth(Zt);
         }
-        Pt = svqb(Pt);
         Tn Yt = mm(Pt, false, M, true);
-        Tn Qt = svqb(svqb(Yt));
+        Tn Qt = orth(Yt);
         Tn X1 = mm(Qt, false, M, false);          // Q^T M   (k x n)
         Tn Bs = mm(X1, false, Pt, true);          // Q^T M P (k x k)
         // Bs row-major == Bs^T col-major: Bs^T = Uj S Vj^T -> Bs = Vj S Uj^T
@@ -417,7 +505,7 @@ struct ctm_ctx {
     }
 
     // projector pair from rhoT (t x rT) and rhoB (rB x t)
-    Projector projector(const Tn& rT, const Tn& rB, int64_t chi)
+    Projector projector(const Tn& rT, const Tn& rB, int64_t chi, int slot)
     {
         const int64_t t = rT.d[0], remT = rT.d[1], remB = rB.d[0];
         REQUIRE(rT.r == 2 && rB.r == 2 && rB.d[1] == t, "projector shapes");
@@ -433,10 +521,10 @@ struct ctm_ctx {
         Tn M = mm(rB, false, rT, false);          // remB x remT
         const int64_t k0 = std::min<int64_t>(chi, std::min(remB, remT));
         Tn UT, S, VT;
-        svd_topk(M, k0, UT, S, VT);
+        svd_topk(M, k0, slot, UT, S, VT);
         // the bond keeps the chi largest singular values that are above the
         // relative cutoff (its numerical rank): one small read-back
-        const double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : 1e-12;
+        const double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : kDefaultCutoff;
         ctmk::count_above(st, S.p, (int)k0, cut, icount);
         int rank = 0;
         HIPCHK(hipMemcpyAsync(&rank, icount, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -461,15 +549,16 @@ struct ctm_ctx {
     }
 
     // ---------------- one symmetric split-CTMRG iteration of one network
-    void step(Net& N, int64_t chi);
+    void step(Net& N, int64_t chi, int net_id);
     void values(Net& N, double* sc_out, bool with_env);
 };
 
 // --------------------------------------------------------------------------
 // the iteration
 // --------------------------------------------------------------------------
-void ctm_ctx::step(Net& N, int64_t chi)
+void ctm_ctx::step(Net& N, int64_t chi, int net_id)
 {
+    const int sl = 6 * net_id;
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
     Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
@@ -500,13 +589,13 @@ void ctm_ctx::step(Net& N, int64_t chi)
     const int64_t xbk = N.xbk, xki = N.xki, xib = N.xib;
     Tn rT1 = perm(upbk, "vetnz->ventz");
     Tn rB1 = perm(upbk, "fbcea->bcfae");
-    Projector P1 = projector(view(rT1, {xbk * D, D * d * xbk}), view(rB1, {D * d * xbk, xbk * D}), chi);
+    Projector P1 = projector(view(rT1, {xbk * D, D * d * xbk}), view(rB1, {D * d * xbk, xbk * D}), chi, sl + 0);
     Tn rT2 = perm(upki, "gpnibh->gibnph");
     Tn rB2 = perm(upib, "jqtnbk->bqjktn");
-    Projector P2 = projector(view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D}), chi);
+    Projector P2 = projector(view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D}), chi, sl + 1);
     Tn rT3 = perm(upib, "jqtnbk->jbqntk");
     Tn rB3 = perm(upki, "gpnibh->bighnp");
-    Projector P3 = projector(view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P}), chi);
+    Projector P3 = projector(view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P}), chi, sl + 2);
     const int64_t c1 = P1.k, c2 = P2.k, c3 = P3.k;
     Tn P1T = view(P1.PT, {c1, xbk, D}), P1B = view(P1.PB, {xbk, D, c1});
     Tn P2T = view(P2.PT, {c2, xki, d, D}), P2B = view(P2.PB, {xki, d, D, c2});
@@ -539,7 +628,7 @@ void ctm_ctx::step(Net& N, int64_t chi)
     // ---- stage 2: half P4 from the two corners
     const int64_t n4 = c1 * D * d;
     Tn rB4 = perm(C4p, "cauXbo->Xbocau");
-    Projector P4 = projector(view(C1p, {n4, n4}), view(rB4, {n4, n4}), chi);
+    Projector P4 = projector(view(C1p, {n4, n4}), view(rB4, {n4, n4}), chi, sl + 3);
 
     // ---- stage 2: P5 (ki) and P6 (ib) from the two-column block
     Tn L = ctr("ykibf,ylg->kibflg", TRpre, K);
@@ -561,8 +650,8 @@ void ctm_ctx::step(Net& N, int64_t chi)
     Tn rT6 = ctr("cfnrst,fbrqsd->cntbqd", UL6, UR6);    // [c3L, Ad1, Od1, Bu2, q2, c3R]
     Tn rB5 = perm(rT6, "gfebca->efgabc");               // rotation image of rho_T6
     Tn rB6 = perm(rT5, "gefcba->efgabc");               // rotation image of rho_T5
-    Projector P5 = projector(view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P}), chi);
-    Projector P6 = projector(view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d}), chi);
+    Projector P5 = projector(view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P}), chi, sl + 4);
+    Projector P6 = projector(view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d}), chi, sl + 5);
     const int64_t k4 = P4.k, k5 = P5.k, k6 = P6.k;
     Tn P4T = view(P4.PT, {k4, c1, D, d}), P4B = view(P4.PB, {c1, D, d, k4});
     Tn P5T = view(P5.PT, {k5, c2, D, P}), P5B = view(P5.PB, {c2, D, P, k5});
@@ -784,6 +873,11 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
     if (!c) { g_init_err = "host allocation failed"; return CTM_ENOMEM; }
     ctm_status s = guarded(c, [&] {
         c->cfg = *cfg;
+        c->profiling = (cfg->flags & CTM_FLAG_PROFILE) != 0;
+        if (const char* e = std::getenv("CTM_JACOBI_EXACT_MAX")) {   // testing aid
+            c->exact_min = std::atoll(e);
+            c->exact_area = c->exact_min * c->exact_min * 4;
+        }
         c->D = cfg->D;
         c->chi = cfg->chi;
         c->xmax = std::max(cfg->chi, 2 * 2 * cfg->D * cfg->D);
@@ -820,8 +914,9 @@ ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_del
         for (int it = 0; it < budget; ++it) {
             // the first move from the product boundary never truncates
             const int64_t chi = (c->iters == 0) ? (int64_t)INT_MAX : (int64_t)c->chi;
-            c->step(c->net[0], chi);
-            c->step(c->net[1], chi);
+            c->step(c->net[0], chi, 0);
+            c->step(c->net[1], chi, 1);
+            HIPCHK(hipGetLastError());
             ++c->iters;
             ++done;
             if (until || it == budget - 1) {
@@ -926,12 +1021,30 @@ ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes
     return CTM_OK;
 }
 
+ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops)
+{
+    if (!c || which < 0 || which > 2) return CTM_EINVAL;
+    if (!c->profiling) { c->err = "context not built with CTM_FLAG_PROFILE"; return CTM_ESTATE; }
+    return guarded(c, [&] {
+        c->prof_collect();
+        if (launches) *launches = c->kstat[which].launches;
+        if (ms) *ms = c->kstat[which].ms;
+        if (flops) *flops = c->kstat[which].flops;
+    });
+}
+
 void ctm_destroy(ctm_ctx* c)
 {
     if (!c) return;
     if (c->st || true) (void)hipStreamSynchronize(c->st);
     c->ws.free_all();
     for (void* p : c->owned) (void)hipFree(p);
+    for (auto& k : c->kstat)
+        for (auto& pr : k.pending) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 

@@ -18,11 +18,23 @@ struct JacobiJob {
     double* V;  // n x n column-major output
     double* S;  // n singular values, descending
     int m, n;
+    int want_v; // 0: do not accumulate V (V output left untouched)
 };
 
 constexpr int kMaxJacobiBatch = 16;
 struct JacobiBatch {            // passed by value as a kernel argument
     JacobiJob job[kMaxJacobiBatch];
+    int n;
+};
+
+struct CholJob {
+    double* G;     // k x k Gram (input; used as workspace when it does not fit in LDS)
+    double* work;  // 2k doubles of workspace (global fallback)
+    double* T;     // k x k output, T = L^-1 D
+    int k;
+};
+struct CholBatch {
+    CholJob job[kMaxJacobiBatch];
     int n;
 };
 
@@ -38,6 +50,7 @@ void eye(hipStream_t s, double* x, int n);
 void symmetrize(hipStream_t s, double* x, int n);
 void scale_lines(hipStream_t s, double* x, int R, int C, const double* f, int mode);
 void inv_sqrt_cut(hipStream_t s, const double* S, double* f, int n, double cutoff);
+void diag_inv_sqrt(hipStream_t s, const double* G, int n, double* d);
 void count_above(hipStream_t s, const double* S, int n, double cutoff, int* out);
 void randn(hipStream_t s, double* x, int64_t n, uint64_t seed);
 void d4_project(hipStream_t s, const double* A, double* out, int D);
@@ -52,6 +65,7 @@ void spectrum_delta(hipStream_t s, double* sv, int n, const double* trace, doubl
 void trace(hipStream_t s, const double* X, int n, double* out);
 void finite_check(hipStream_t s, const double* x, int64_t n, int* flag);
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps);
+void cholqr(hipStream_t s, const CholBatch& jobs, double shift);
 
 constexpr int kRedBlocks = 256;  // partial-sum slots needed by dot()
 

@@ -302,6 +302,20 @@ void inv_sqrt_cut(hipStream_t s, const double* S, double* f, int n, double cutof
     hipLaunchKernelGGL(inv_sqrt_cut_kernel, dim3(1), dim3(256), 0, s, S, f, n, cutoff);
 }
 
+// d[i] = G[i][i]^-1/2 (0 for a zero diagonal)
+__global__ void diag_inv_sqrt_kernel(const double* __restrict__ G, int n, double* d)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = G[(int64_t)i * n + i];
+        d[i] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    }
+}
+
+void diag_inv_sqrt(hipStream_t s, const double* G, int n, double* d)
+{
+    hipLaunchKernelGGL(diag_inv_sqrt_kernel, dim3(1), dim3(256), 0, s, G, n, d);
+}
+
 // out = #{i < n : S[i] > cutoff * S[0]}  (S descending)
 __global__ void count_above_kernel(const double* __restrict__ S, int n, double cutoff, int* out)
 {
@@ -532,13 +546,22 @@ void finite_check(hipStream_t s, const double* x, int64_t n, int* flag)
 // Output U: m x n column-major (unit columns, 0 where sigma = 0), V: n x n
 //        column-major, S: n, sorted descending (ties by column index):
 //        X = U diag(S) V^T.
-// Work:  W (n x n) holds V during the sweeps.
+// Work:  W (n x n) holds V during the sweeps.  When m * n doubles fit in LDS
+//        the columns of X are rotated there.
+// A pair (p, q) is rotated while |x_p . x_q| > tol * |x_p| |x_q| with
+// tol = 2 sqrt(m) eps (the rounding level of the dot product itself).
+constexpr int kJacobiLdsDoubles = 18432;   // 144 KiB of the 160 KiB LDS
+
 __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int max_sweeps)
 {
+    extern __shared__ double lds[];
     const JacobiJob jb = jobs.job[blockIdx.x];
-    double* X = jb.X;
-    double* W = jb.W;
     const int m = jb.m, n = jb.n;
+    const bool acc_v = jb.want_v != 0;
+    const bool x_lds = (int64_t)m * n <= kJacobiLdsDoubles;
+    const bool w_lds = acc_v && (int64_t)m * n + (int64_t)n * n <= kJacobiLdsDoubles;
+    double* X = x_lds ? lds : jb.X;
+    double* W = w_lds ? lds + (int64_t)m * n : jb.W;
     const int ne = n + (n & 1);
     const int npairs = ne / 2;
     const int nthr = blockDim.x;
@@ -550,11 +573,32 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
     __shared__ double sig[1024];
     __shared__ int rnk[1024];
 
-    for (int64_t i = threadIdx.x; i < (int64_t)n * n; i += nthr)
-        W[i] = ((i / n) == (i % n)) ? 1.0 : 0.0;
+    __shared__ double fro2;
+    if (x_lds)
+        for (int64_t i = threadIdx.x; i < (int64_t)m * n; i += nthr) X[i] = jb.X[i];
+    if (acc_v)
+        for (int64_t i = threadIdx.x; i < (int64_t)n * n; i += nthr)
+            W[i] = ((i / n) == (i % n)) ? 1.0 : 0.0;
     __syncthreads();
+    // ||X||_F^2 (invariant under the rotations): columns below ~eps ||X||_F are
+    // rounding noise and are left alone (they would never test orthogonal)
+    for (int j = gid; j < n; j += ngroups) {
+        const double* xj = X + (int64_t)j * m;
+        double v = 0.0;
+        for (int r = gl; r < m; r += G) v += xj[r] * xj[r];
+        for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+        if (gl == 0) sig[j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int j = 0; j < n; ++j) t += sig[j];
+        fro2 = t;
+    }
+    __syncthreads();
+    const double noise2 = 1e-30 * fro2;
 
-    const double eps = 1e-15;
+    const double tol = 2.0 * sqrt((double)m) * 2.220446049250313e-16;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         if (threadIdx.x == 0) rotated = 0;
         __syncthreads();
@@ -579,7 +623,7 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
                     be += __shfl_xor(be, o, G);
                     ga += __shfl_xor(ga, o, G);
                 }
-                if (ga != 0.0 && al > 0.0 && be > 0.0 && fabs(ga) > eps * sqrt(al * be)) {
+                if (ga != 0.0 && al > noise2 && be > noise2 && fabs(ga) > tol * sqrt(al * be)) {
                     const double zeta = (be - al) / (2.0 * ga);
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
@@ -588,12 +632,14 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
                         xp[r] = c * a - sn * b;
                         xq[r] = sn * a + c * b;
                     }
-                    double* wp = W + (int64_t)p * n;
-                    double* wq = W + (int64_t)q * n;
-                    for (int r = gl; r < n; r += G) {
-                        const double a = wp[r], b = wq[r];
-                        wp[r] = c * a - sn * b;
-                        wq[r] = sn * a + c * b;
+                    if (acc_v) {
+                        double* wp = W + (int64_t)p * n;
+                        double* wq = W + (int64_t)q * n;
+                        for (int r = gl; r < n; r += G) {
+                            const double a = wp[r], b = wq[r];
+                            wp[r] = c * a - sn * b;
+                            wq[r] = sn * a + c * b;
+                        }
                     }
                     if (gl == 0) rotated = 1;
                 }
@@ -629,9 +675,11 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
         const double* xj = X + (int64_t)j * m;
         double* uo = jb.U + (int64_t)dst * m;
         for (int r = gl; r < m; r += G) uo[r] = xj[r] * inv;
-        const double* wj = W + (int64_t)j * n;
-        double* vo = jb.V + (int64_t)dst * n;
-        for (int r = gl; r < n; r += G) vo[r] = wj[r];
+        if (acc_v) {
+            const double* wj = W + (int64_t)j * n;
+            double* vo = jb.V + (int64_t)dst * n;
+            for (int r = gl; r < n; r += G) vo[r] = wj[r];
+        }
         if (gl == 0) jb.S[dst] = sj;
     }
 }
@@ -639,7 +687,110 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
 {
     if (jobs.n <= 0) return;
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(jobs.n), dim3(1024), 0, s, jobs, max_sweeps);
+    int64_t need = 0;
+    for (int i = 0; i < jobs.n; ++i) {
+        const int64_t mn = (int64_t)jobs.job[i].m * jobs.job[i].n;
+        const int64_t nn = jobs.job[i].want_v ? (int64_t)jobs.job[i].n * jobs.job[i].n : 0;
+        int64_t use = 0;
+        if (mn + nn <= kJacobiLdsDoubles) use = mn + nn;
+        else if (mn <= kJacobiLdsDoubles) use = mn;
+        if (use > need) need = use;
+    }
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(jobs.n), dim3(1024), need * sizeof(double), s, jobs, max_sweeps);
+}
+
+// ---------------------------------------------------------------------------
+// shifted Cholesky QR factor, one workgroup per problem
+// ---------------------------------------------------------------------------
+// Input  G: k x k Gram matrix Y Y^T of the k rows of Y (row-major, global).
+// Output T: k x k lower-triangular, T = L^-1 D with D = diag(G)^-1/2 and
+//        L L^T = D G D + shift I, so that the rows of T Y are orthonormal
+//        (up to the shift).  G lives in LDS when k*k (+k) doubles fit.
+__global__ __launch_bounds__(1024) void cholqr_kernel(CholBatch jobs, double shift)
+{
+    extern __shared__ double lds[];
+    const CholJob jb = jobs.job[blockIdx.x];
+    const int k = jb.k;
+    const bool in_lds = (int64_t)k * k + 2 * k <= kJacobiLdsDoubles;
+    double* A = in_lds ? lds : jb.G;                 // working copy (lower = L)
+    double* dsc = in_lds ? lds + (int64_t)k * k : jb.work;
+    double* dinv = dsc + k;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    for (int i = tid; i < k; i += nthr) {
+        const double v = jb.G[(int64_t)i * k + i];
+        dsc[i] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    }
+    __syncthreads();
+    // A = D G D + shift I (lower triangle incl. diagonal)
+    for (int64_t e = tid; e < (int64_t)k * k; e += nthr) {
+        const int i = (int)(e / k), l = (int)(e % k);
+        if (l <= i) A[e] = jb.G[e] * dsc[i] * dsc[l] + (i == l ? shift : 0.0);
+    }
+    __syncthreads();
+    // right-looking Cholesky, one barrier per column: step j updates the
+    // trailing lower triangle with the unscaled column j and scales column j-1
+    for (int j = 0; j < k; ++j) {
+        const double ajj = A[(int64_t)j * k + j];
+        const double inv = ajj > 0.0 ? 1.0 / ajj : 0.0;   // 1 / L_jj^2
+        const int nt = k - 1 - j;
+        const int64_t ntri = (int64_t)nt * (nt + 1) / 2;
+        for (int64_t e = tid; e < ntri; e += nthr) {
+            // e -> (i, l) with j < l <= i < k
+            const int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+            int i0 = ii, l0 = (int)(e - (int64_t)ii * (ii + 1) / 2);
+            if (l0 > i0) { ++i0; l0 = (int)(e - (int64_t)i0 * (i0 + 1) / 2); }
+            if (l0 < 0) { --i0; l0 = (int)(e - (int64_t)i0 * (i0 + 1) / 2); }
+            const int i = j + 1 + i0, l = j + 1 + l0;
+            A[(int64_t)i * k + l] -= A[(int64_t)i * k + j] * A[(int64_t)l * k + j] * inv;
+        }
+        if (j > 0) {
+            const int jm = j - 1;
+            const double lj = sqrt(fmax(A[(int64_t)jm * k + jm], 0.0));
+            const double li = lj > 0.0 ? 1.0 / lj : 0.0;
+            for (int i = jm + 1 + tid; i < k; i += nthr) A[(int64_t)i * k + jm] *= li;
+        }
+        __syncthreads();
+        if (tid == 0 && j > 0) A[(int64_t)(j - 1) * k + (j - 1)] = sqrt(fmax(A[(int64_t)(j - 1) * k + (j - 1)], 0.0));
+        __syncthreads();
+    }
+    {
+        const int jm = k - 1;
+        if (tid == 0) A[(int64_t)jm * k + jm] = sqrt(fmax(A[(int64_t)jm * k + jm], 0.0));
+        __syncthreads();
+    }
+    // L^-1 by columns: thread c solves L x = e_c, x_i stored at A[c][i] (i > c)
+    for (int c = tid; c < k; c += nthr) {
+        const double lcc = A[(int64_t)c * k + c];
+        const double xc = lcc > 0.0 ? 1.0 / lcc : 0.0;
+        dinv[c] = xc;
+        for (int i = c + 1; i < k; ++i) {
+            double sacc = A[(int64_t)i * k + c] * xc;
+            for (int jj = c + 1; jj < i; ++jj) sacc += A[(int64_t)i * k + jj] * A[(int64_t)c * k + jj];
+            const double lii = A[(int64_t)i * k + i];
+            A[(int64_t)c * k + i] = lii > 0.0 ? -sacc / lii : 0.0;
+        }
+    }
+    __syncthreads();
+    // T[i][c] = (L^-1)[i][c] d_c
+    for (int64_t e = tid; e < (int64_t)k * k; e += nthr) {
+        const int i = (int)(e / k), c = (int)(e % k);
+        double v = 0.0;
+        if (i == c) v = dinv[c];
+        else if (i > c) v = A[(int64_t)c * k + i];
+        jb.T[e] = v * dsc[c];
+    }
+}
+
+void cholqr(hipStream_t s, const CholBatch& jobs, double shift)
+{
+    if (jobs.n <= 0) return;
+    int64_t need = 0;
+    for (int i = 0; i < jobs.n; ++i) {
+        const int64_t kk = jobs.job[i].k;
+        if (kk * kk + 2 * kk <= kJacobiLdsDoubles && kk * kk + 2 * kk > need) need = kk * kk + 2 * kk;
+    }
+    hipLaunchKernelGGL(cholqr_kernel, dim3(jobs.n), dim3(1024), need * sizeof(double), s, jobs, shift);
 }
 
 }  // namespace ctmk
+

@@ -44,7 +44,7 @@ int ctm_selftest_jacobi(int m, int n, const double* X, double* U, double* S, dou
     if (!dX || !dW || !dU || !dV || !dS) return 1;
     ctmk::JacobiBatch jb{};
     jb.n = 1;
-    jb.job[0] = ctmk::JacobiJob{dX, dW, dU, dV, dS, m, n};
+    jb.job[0] = ctmk::JacobiJob{dX, dW, dU, dV, dS, m, n, 1};
     ctmk::jacobi_svd(nullptr, jb, 40);
     int rc = hipDeviceSynchronize() != hipSuccess;
     rc |= hipMemcpy(U, dU, (size_t)m * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;

@@ -15,6 +15,7 @@ LIB_NAME = "libctm.so"
 
 CTM_FP64, CTM_FP32, CTM_BF16 = 0, 1, 2
 CTM_FLAG_DEVICE_PTRS = 1
+CTM_FLAG_PROFILE = 2
 
 STATUS = {0: "CTM_OK", 1: "CTM_EINVAL", 2: "CTM_ENOMEM", 3: "CTM_EDEVICE",
           4: "CTM_ENOCONV", 5: "CTM_ENUMERIC", 6: "CTM_ESTATE"}
@@ -58,6 +59,8 @@ def load_library(path=None):
     lib.ctm_corner_spectrum.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.ctm_reset_tensor.argtypes = [vp, ctypes.c_double, vp]
     lib.ctm_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong)]
+    lib.ctm_kernel_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), dp, dp]
+    lib.ctm_kernel_stats.restype = ctypes.c_int
     lib.ctm_destroy.argtypes = [vp]
     lib.ctm_destroy.restype = None
     lib.ctm_last_error.argtypes = [vp]
@@ -91,11 +94,13 @@ class SplitCTM:
     """
 
     def __init__(self, beta, A, chi, max_iter=100, tol=0.0, precision=CTM_FP64,
-                 power_iters=0, svd_cutoff=0.0, stream=None, lib=None):
+                 power_iters=0, svd_cutoff=0.0, stream=None, lib=None, profile=False):
         self._lib = lib or load_library()
         self._ctx = ctypes.c_void_p()
         D = int(np.shape(A)[1])
         flags, ptr, keep = self._tensor_arg(A)
+        if profile:
+            flags |= CTM_FLAG_PROFILE
         cfg = _Config(D, int(chi), int(max_iter), float(tol), int(precision), flags,
                       int(power_iters), float(svd_cutoff))
         st = self._lib.ctm_init(ctypes.byref(cfg), float(beta), ptr,
@@ -155,10 +160,18 @@ class SplitCTM:
 
     def reset_tensor(self, beta, A):
         flags, ptr, keep = self._tensor_arg(A)
-        if flags != self._flags:
+        if flags != (self._flags & CTM_FLAG_DEVICE_PTRS):
             raise ValueError("A must live where the context's A lived (host vs device)")
         self._check(self._lib.ctm_reset_tensor(self._ctx, float(beta), ptr))
         self.beta = float(beta)
+
+    def kernel_stats(self, which):
+        """(launches, total ms, algorithmic flops) of kernel class which (0 GEMM, 1 Jacobi)."""
+        n = ctypes.c_longlong(0)
+        ms = ctypes.c_double(0.0)
+        fl = ctypes.c_double(0.0)
+        self._check(self._lib.ctm_kernel_stats(self._ctx, int(which), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+        return n.value, ms.value, fl.value
 
     def query(self):
         it = ctypes.c_int(0)

@@ -13,13 +13,17 @@ import numpy as np
 
 PHYS = 2
 
-# name -> (beta, D, chi, max_iter, tol, precision)
+# name -> beta, D, chi, iteration cap / tolerance, precision, seed; svd_cutoff is
+# the relative pseudo-inverse cutoff of the projector construction (both sides)
 WORKLOADS = {
-    "d2_chi16": dict(beta=0.20, D=2, chi=16, max_iter=40, tol=0.0, prec="fp64", seed=0),
-    "d4_chi64": dict(beta=0.2216, D=4, chi=64, max_iter=200, tol=1e-9, prec="fp32", seed=0),
+    "d2_chi16": dict(beta=0.20, D=2, chi=16, max_iter=40, tol=0.0, prec="fp64", seed=0,
+                     svd_cutoff=1e-8),
+    "d4_chi64": dict(beta=0.2216, D=4, chi=64, max_iter=200, tol=1e-9, prec="fp32", seed=0,
+                     svd_cutoff=1e-8),
     "d5_chi100": dict(beta=0.22, D=5, chi=100, max_iter=200, tol=1e-9, prec="fp64", seed=0,
-                      fp32_params=True),
-    "d6_chi144": dict(beta=0.22, D=6, chi=144, max_iter=200, tol=1e-9, prec="bf16", seed=0),
+                      fp32_params=True, svd_cutoff=1e-8),
+    "d6_chi144": dict(beta=0.22, D=6, chi=144, max_iter=200, tol=1e-9, prec="bf16", seed=0,
+                      svd_cutoff=1e-8),
 }
 
 

@@ -16,7 +16,7 @@ from synth_inputs import WORKLOADS, raw_peps
 pytestmark = pytest.mark.gpu
 
 
-def oracle_run(beta, A, chi, n_iter, cutoff=1e-12):
+def oracle_run(beta, A, chi, n_iter, cutoff=1e-8):
     As = model.d4_symmetrize(A)
     O3, O2 = model.pepo_O(beta), model.identity_pepo()
     e3, _, _, _ = split.run(As, O3, chi, n_iter, cutoff=cutoff)
@@ -27,8 +27,11 @@ def oracle_run(beta, A, chi, n_iter, cutoff=1e-12):
     return -(l3 - l2) / beta, l3, l2, g, split.corner_spectrum(e3), split.corner_spectrum(e2)
 
 
-def gpu_run(beta, A, chi, n_iter):
-    with ctm.SplitCTM(beta, A, chi) as c:
+CUT = 1e-8   # relative pseudo-inverse cutoff, the same on both sides
+
+
+def gpu_run(beta, A, chi, n_iter, cutoff=CUT):
+    with ctm.SplitCTM(beta, A, chi, svd_cutoff=cutoff) as c:
         done, _, _ = c.iterate(n_iter)
         assert done == n_iter
         f, l3, l2 = c.free_energy()
@@ -110,3 +113,28 @@ def test_warm_restart_and_determinism():
         c.iterate(5)
         f2, _, _ = c.free_energy()
     assert abs(f1 - f2) < 1e-10 * abs(f1)
+
+
+def test_subspace_svd_path_d3_chi64():
+    """Bonds of chi D d = 384 > 256 use the warm-started subspace-iteration SVD;
+    after 30 iterations the result still matches the oracle's LAPACK SVDs."""
+    A = raw_peps(3, 0)
+    got = gpu_run(0.22, A, 64, 30)
+    ref = oracle_run(0.22, A, 64, 30)
+    assert abs(got[0] - ref[0]) <= 1e-9 * abs(ref[0]), (got[0], ref[0])
+    assert np.linalg.norm(got[3] - ref[3]) <= 1e-6 * np.linalg.norm(ref[3])
+
+
+def test_d5_chi100_against_stored_oracle_reference():
+    """The benchmark workload (beta = 0.22, D = 5, chi = 100) after 30
+    iterations, against tests/golden/d5_chi100_it30.npz written by
+    tests/golden/make_reference.py from the oracle.  The GPU factorises the
+    1000-dimensional projector problems by warm-started subspace iteration, the
+    oracle by LAPACK; the bar is 1e-8 relative on f and 1e-5 on g."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "d5_chi100_it30.npz"))
+    w = WORKLOADS["d5_chi100"]
+    from synth_inputs import workload_peps
+    f, l3, l2, g, s3, s2 = gpu_run(w["beta"], workload_peps("d5_chi100"), w["chi"], 30)
+    assert abs(f - float(ref["f"])) <= 1e-8 * abs(float(ref["f"])), (f, float(ref["f"]))
+    assert np.linalg.norm(g - ref["g"]) <= 1e-5 * np.linalg.norm(ref["g"])
