@@ -189,6 +189,8 @@ struct ctm_ctx {
     double* part = nullptr;          // reduction partials
     double* scal = nullptr;          // scratch scalars
     int* icount = nullptr;           // device int for rank read-back
+    double* gws = nullptr;           // split-K partial products of the GEMMs
+    int64_t gws_cap = 0;
     Net net[2];                      // [0] triple, [1] double
     int iters = 0;
     uint64_t svd_calls = 0;
@@ -243,7 +245,8 @@ struct ctm_ctx {
               int64_t sC, int64_t nb)
     {
         hipEvent_t e = prof_begin();
-        ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, (int)nb);
+        ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, (int)nb,
+                       gws, gws_cap);
         prof_end(0, e, 2.0 * (double)M * (double)N * (double)K * (double)nb);
     }
     struct Warm { double* V = nullptr; int64_t cap = 0, n = 0, k = 0; };
@@ -418,7 +421,7 @@ struct ctm_ctx {
         S = tmp({n});
         ctmk::JacobiBatch jb{};
         jb.n = 1;
-        jb.job[0] = ctmk::JacobiJob{X.p, W.p, U.p, V.p, S.p, (int)m, (int)n, want_v ? 1 : 0};
+        jb.job[0] = ctmk::JacobiJob{X.p, W.p, U.p, V.p, S.p, (int)m, (int)n, want_v ? 1 : 0, nullptr};
         hipEvent_t e = prof_begin();
         ctmk::jacobi_svd(st, jb, kJacobiSweeps);
         prof_end(1, e, 0.0);
@@ -887,6 +890,8 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
         c->part = c->keep(ctmk::kRedBlocks);
         c->scal = c->keep(16);
         c->icount = (int*)c->keep(1);
+        c->gws_cap = (int64_t)1 << 22;   // 32 MiB
+        c->gws = c->keep(c->gws_cap);
         init_net(c, c->net[0], 2);
         init_net(c, c->net[1], 1);
         load_tensor(c, beta, A);

@@ -2,7 +2,8 @@
 //
 //   gemm_f64      batched C = alpha op(A) op(B) + beta C on the FP64 matrix cores
 //                 (v_mfma_f64_16x16x4_f64): 64x64 block tile, four 64-wide
-//                 waves of 32x32, K staged through LDS 16 at a time.
+//                 waves of 32x32, K staged through LDS 32 at a time, split-K
+//                 with a deterministic reduction when the tile grid is small.
 //   permute       dense tensor transposition (generic rank <= 8).
 //   dot / norms   deterministic two-pass reductions to device scalars.
 //   jacobi_svd    one-sided (Hestenes) Jacobi SVD, one workgroup per matrix,
@@ -11,6 +12,8 @@
 //                 D4 projection of the PEPS tensor / Ising PEPO / scalar algebra.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "kernels.h"
 
@@ -22,26 +25,34 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // GEMM (FP64 MFMA)
 // ---------------------------------------------------------------------------
 // A(m,k) = TA ? A[k*lda + m] : A[m*lda + k];  B(k,n) = TB ? B[n*ldb + k] : B[k*ldb + n]
-// C(m,n) = C[m*ldc + n].  blockIdx.z selects the batch entry.
+// C(m,n) = C[m*ldc + n].  blockIdx.z = batch entry * ksplit + K slice.
 // MFMA 16x16x4 f64 operand layout (lane l of a 64-wide wave):
 //   a = A[row = l%16][k = l/16],  b = B[k = l/16][col = l%16],
 //   acc[r] = C[row = l/16 + 4*r][col = l%16].
+// The next K step is fetched into registers while the matrix cores work on
+// the current one (one LDS stage, register double buffer).  With ksplit > 1
+// each K slice writes alpha * (its partial product) to P[z][M][N] and
+// gemm_reduce_kernel sums the slices into C (beta must be 0 then).
 constexpr int GT = 64;   // block tile (M and N)
-constexpr int GK = 16;   // K step held in LDS
+constexpr int GK = 32;   // K step held in LDS
+constexpr int GL = (GT * GK) / 256;   // elements of each operand a thread stages per step
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int M, int N, int K, double alpha,
     const double* __restrict__ A, int64_t lda, int64_t sA,
     const double* __restrict__ B, int64_t ldb, int64_t sB,
-    double beta, double* __restrict__ C, int64_t ldc, int64_t sC)
+    double beta, double* __restrict__ C, int64_t ldc, int64_t sC,
+    int ksplit, int kchunk, double* __restrict__ P)
 {
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
-    const int bz = blockIdx.z;
+    const int z = blockIdx.z;
+    const int bz = z / ksplit, sp = z % ksplit;
     A += bz * sA;
     B += bz * sB;
-    C += bz * sC;
+    const int kbeg = sp * kchunk;
+    const int kend = min(K, kbeg + kchunk);
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -49,35 +60,54 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < K; k0 += GK) {
+    double ra[GL], rb[GL];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int t = 0; t < (GT * GK) / 256; ++t) {
+        for (int t = 0; t < GL; ++t) {
             const int e = tid + t * 256;
             int mm, kk;
             if (!TA) { kk = e % GK; mm = e / GK; } else { mm = e % GT; kk = e / GT; }
             const int gm = m0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < M && gk < K) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-            As[kk][mm] = v;
+            ra[t] = (gm < M && gk < kend) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.0;
         }
 #pragma unroll
-        for (int t = 0; t < (GT * GK) / 256; ++t) {
+        for (int t = 0; t < GL; ++t) {
             const int e = tid + t * 256;
             int nn, kk;
             if (!TB) { nn = e % GT; kk = e / GT; } else { kk = e % GK; nn = e / GK; }
             const int gn = n0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gn < N && gk < K) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-            Bs[kk][nn] = v;
+            rb[t] = (gn < N && gk < kend) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.0;
         }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int t = 0; t < GL; ++t) {
+            const int e = tid + t * 256;
+            int mm, kk;
+            if (!TA) { kk = e % GK; mm = e / GK; } else { mm = e % GT; kk = e / GT; }
+            As[kk][mm] = ra[t];
+        }
+#pragma unroll
+        for (int t = 0; t < GL; ++t) {
+            const int e = tid + t * 256;
+            int nn, kk;
+            if (!TB) { nn = e % GT; kk = e / GT; } else { kk = e % GK; nn = e / GK; }
+            Bs[kk][nn] = rb[t];
+        }
+    };
+
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        stage();
         __syncthreads();
+        if (k0 + GK < kend) fetch(k0 + GK);
 #pragma unroll
         for (int kk = 0; kk < GK; kk += 4) {
             const int kq = kk + (lane >> 4);
-            double a0 = As[kq][wm * 32 + (lane & 15)];
-            double a1 = As[kq][wm * 32 + 16 + (lane & 15)];
-            double b0 = Bs[kq][wn * 32 + (lane & 15)];
-            double b1 = Bs[kq][wn * 32 + 16 + (lane & 15)];
+            const double a0 = As[kq][wm * 32 + (lane & 15)];
+            const double a1 = As[kq][wm * 32 + 16 + (lane & 15)];
+            const double b0 = Bs[kq][wn * 32 + (lane & 15)];
+            const double b1 = Bs[kq][wn * 32 + 16 + (lane & 15)];
             acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -85,6 +115,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         }
         __syncthreads();
     }
+    double* out;
+    int64_t ldo;
+    if (ksplit > 1) { out = P + (int64_t)z * M * N; ldo = N; }
+    else { out = C + bz * sC; ldo = ldc; }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -94,28 +128,64 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
                 const int gm = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
                 const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (gm < M && gn < N) {
-                    double* c = C + (int64_t)gm * ldc + gn;
+                    double* c = out + (int64_t)gm * ldo + gn;
                     const double v = alpha * acc[i][j][r];
-                    *c = (beta == 0.0) ? v : v + beta * (*c);
+                    *c = (beta == 0.0 || ksplit > 1) ? v : v + beta * (*c);
                 }
             }
 }
 
+// C[b][m][n] = sum over the ksplit slices of P[b * ksplit + s][m][n]
+__global__ void gemm_reduce_kernel(const double* __restrict__ P, int M, int N, int ksplit,
+                                   double* __restrict__ C, int64_t ldc, int64_t sC, int64_t total)
+{
+    const int64_t mn = (int64_t)M * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / mn, e = i % mn;
+        const double* p = P + b * ksplit * mn + e;
+        double v = 0.0;
+        for (int s = 0; s < ksplit; ++s) v += p[s * mn];
+        C[b * sC + (e / N) * ldc + (e % N)] = v;
+    }
+}
+
+int gemm_split_plan(int M, int N, int K, int batch, int64_t ws_cap)
+{
+    const int64_t tiles = (int64_t)((N + GT - 1) / GT) * ((M + GT - 1) / GT) * batch;
+    if (tiles >= 160 || K < 4 * GK) return 1;
+    int s = (int)std::min<int64_t>((320 + tiles - 1) / tiles, K / (2 * GK));
+    while (s > 1 && (int64_t)s * M * N * batch > ws_cap) --s;
+    return std::max(s, 1);
+}
+
 void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
               const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
-              double beta, double* C, int64_t ldc, int64_t sC, int batch)
+              double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return;
-    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, batch);
+    int ksplit = (beta == 0.0 && ws) ? gemm_split_plan(M, N, K, batch, ws_cap) : 1;
+    int kchunk = K;
+    if (ksplit > 1) {
+        kchunk = (((K + ksplit - 1) / ksplit) + GK - 1) / GK * GK;
+        ksplit = (K + kchunk - 1) / kchunk;
+    }
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, batch * ksplit);
     dim3 block(256);
+    double* P = ksplit > 1 ? ws : nullptr;
     if (!ta && !tb)
-        hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+        hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
     else if (ta && !tb)
-        hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+        hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
     else if (!ta && tb)
-        hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+        hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
     else
-        hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+        hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
+    if (ksplit > 1) {
+        const int64_t total = (int64_t)batch * M * N;
+        const int g = (int)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(gemm_reduce_kernel, dim3(g), dim3(256), 0, s, P, M, N, ksplit, C, ldc, sC, total);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -551,17 +621,45 @@ void finite_check(hipStream_t s, const double* x, int64_t n, int* flag)
 // A pair (p, q) is rotated while |x_p . x_q| > tol * |x_p| |x_q| with
 // tol = 2 sqrt(m) eps (the rounding level of the dot product itself).
 constexpr int kJacobiLdsDoubles = 18432;   // 144 KiB of the 160 KiB LDS
+constexpr int kCholLdsDoubles = 20224;     // 158 KiB
 
+// (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q) over len entries, the G lanes of
+// a group striding by G.  Loads are batched ahead of the stores (the columns
+// are distinct) so that their latency is paid once per batch.
+__device__ inline void rotate_pair(double* __restrict__ xp, double* __restrict__ xq, int len,
+                                   int gl, int G, double c, double sn)
+{
+    constexpr int RB = 12;
+    for (int r0 = gl; r0 < len; r0 += RB * G) {
+        double a[RB], b[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int r = r0 + u * G;
+            a[u] = r < len ? xp[r] : 0.0;
+            b[u] = r < len ? xq[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int r = r0 + u * G;
+            if (r < len) {
+                xp[r] = c * a[u] - sn * b[u];
+                xq[r] = sn * a[u] + c * b[u];
+            }
+        }
+    }
+}
+
+// XL / WL: X / W live in LDS (decided per batch on the host, so that every
+// access compiles to LDS or global instructions instead of flat ones).
+template <bool XL, bool WL>
 __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int max_sweeps)
 {
     extern __shared__ double lds[];
     const JacobiJob jb = jobs.job[blockIdx.x];
     const int m = jb.m, n = jb.n;
     const bool acc_v = jb.want_v != 0;
-    const bool x_lds = (int64_t)m * n <= kJacobiLdsDoubles;
-    const bool w_lds = acc_v && (int64_t)m * n + (int64_t)n * n <= kJacobiLdsDoubles;
-    double* X = x_lds ? lds : jb.X;
-    double* W = w_lds ? lds + (int64_t)m * n : jb.W;
+    double* X = XL ? lds : jb.X;
+    double* W = WL ? lds + (int64_t)m * n : jb.W;
     const int ne = n + (n & 1);
     const int npairs = ne / 2;
     const int nthr = blockDim.x;
@@ -574,7 +672,7 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
     __shared__ int rnk[1024];
 
     __shared__ double fro2;
-    if (x_lds)
+    if (XL)
         for (int64_t i = threadIdx.x; i < (int64_t)m * n; i += nthr) X[i] = jb.X[i];
     if (acc_v)
         for (int64_t i = threadIdx.x; i < (int64_t)n * n; i += nthr)
@@ -627,27 +725,19 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
                     const double zeta = (be - al) / (2.0 * ga);
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                    for (int r = gl; r < m; r += G) {
-                        const double a = xp[r], b = xq[r];
-                        xp[r] = c * a - sn * b;
-                        xq[r] = sn * a + c * b;
-                    }
-                    if (acc_v) {
-                        double* wp = W + (int64_t)p * n;
-                        double* wq = W + (int64_t)q * n;
-                        for (int r = gl; r < n; r += G) {
-                            const double a = wp[r], b = wq[r];
-                            wp[r] = c * a - sn * b;
-                            wq[r] = sn * a + c * b;
-                        }
-                    }
+                    rotate_pair(xp, xq, m, gl, G, c, sn);
+                    if (acc_v) rotate_pair(W + (int64_t)p * n, W + (int64_t)q * n, n, gl, G, c, sn);
                     if (gl == 0) rotated = 1;
                 }
             }
             __syncthreads();
         }
-        if (rotated == 0) break;
+        if (rotated == 0) {
+            if (jb.sweeps && threadIdx.x == 0) jb.sweeps[0] = sweep + 1;
+            break;
+        }
         __syncthreads();
+        if (sweep + 1 == max_sweeps && jb.sweeps && threadIdx.x == 0) jb.sweeps[0] = max_sweeps;
     }
     // singular values = column norms
     for (int j = gid; j < n; j += ngroups) {
@@ -687,16 +777,22 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
 {
     if (jobs.n <= 0) return;
-    int64_t need = 0;
+    bool xl = true, wl = true;
+    int64_t need_x = 0, need_w = 0;
     for (int i = 0; i < jobs.n; ++i) {
         const int64_t mn = (int64_t)jobs.job[i].m * jobs.job[i].n;
         const int64_t nn = jobs.job[i].want_v ? (int64_t)jobs.job[i].n * jobs.job[i].n : 0;
-        int64_t use = 0;
-        if (mn + nn <= kJacobiLdsDoubles) use = mn + nn;
-        else if (mn <= kJacobiLdsDoubles) use = mn;
-        if (use > need) need = use;
+        xl = xl && mn <= kJacobiLdsDoubles;
+        wl = wl && mn + nn <= kJacobiLdsDoubles;
+        need_x = std::max(need_x, mn);
+        need_w = std::max(need_w, mn + nn);
     }
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(jobs.n), dim3(1024), need * sizeof(double), s, jobs, max_sweeps);
+    if (xl && wl)
+        hipLaunchKernelGGL((jacobi_svd_kernel<true, true>), dim3(jobs.n), dim3(1024), need_w * sizeof(double), s, jobs, max_sweeps);
+    else if (xl)
+        hipLaunchKernelGGL((jacobi_svd_kernel<true, false>), dim3(jobs.n), dim3(1024), need_x * sizeof(double), s, jobs, max_sweeps);
+    else
+        hipLaunchKernelGGL((jacobi_svd_kernel<false, false>), dim3(jobs.n), dim3(1024), 0, s, jobs, max_sweeps);
 }
 
 // ---------------------------------------------------------------------------
@@ -705,79 +801,65 @@ void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
 // Input  G: k x k Gram matrix Y Y^T of the k rows of Y (row-major, global).
 // Output T: k x k lower-triangular, T = L^-1 D with D = diag(G)^-1/2 and
 //        L L^T = D G D + shift I, so that the rows of T Y are orthonormal
-//        (up to the shift).  G lives in LDS when k*k (+k) doubles fit.
+//        (up to the shift).  The work lives in LDS when k*k + 2k doubles fit.
+//        Non-positive pivots (rank deficiency beyond the shift) give zero rows.
+template <bool IN_LDS>
 __global__ __launch_bounds__(1024) void cholqr_kernel(CholBatch jobs, double shift)
 {
     extern __shared__ double lds[];
     const CholJob jb = jobs.job[blockIdx.x];
     const int k = jb.k;
-    const bool in_lds = (int64_t)k * k + 2 * k <= kJacobiLdsDoubles;
-    double* A = in_lds ? lds : jb.G;                 // working copy (lower = L)
-    double* dsc = in_lds ? lds + (int64_t)k * k : jb.work;
+    double* A = IN_LDS ? lds : jb.G;                 // working matrix
+    double* dsc = IN_LDS ? lds + (int64_t)k * k : jb.work;
     double* dinv = dsc + k;
     const int nthr = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
     for (int i = tid; i < k; i += nthr) {
         const double v = jb.G[(int64_t)i * k + i];
         dsc[i] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
     }
     __syncthreads();
-    // A = D G D + shift I (lower triangle incl. diagonal)
+    // lower triangle: D G D + shift I; strict upper triangle: 0 (X = identity)
     for (int64_t e = tid; e < (int64_t)k * k; e += nthr) {
         const int i = (int)(e / k), l = (int)(e % k);
-        if (l <= i) A[e] = jb.G[e] * dsc[i] * dsc[l] + (i == l ? shift : 0.0);
+        A[e] = (l <= i) ? jb.G[e] * dsc[i] * dsc[l] + (i == l ? shift : 0.0) : 0.0;
     }
     __syncthreads();
-    // right-looking Cholesky, one barrier per column: step j updates the
-    // trailing lower triangle with the unscaled column j and scales column j-1
+    // Gaussian elimination without pivoting (LDL^T): the lower triangle holds
+    // the Schur complement, the strict upper triangle the unit lower-triangular
+    // elimination matrix X transposed (X_ic at A[c][i]), so that X A0 X^T =
+    // diag(p) with the pivots p on the diagonal, and L^-1 = diag(p)^-1/2 X.
+    // Step j, row i > j, with f = A_ij / A_jj, touches in one sweep over e <= i:
+    //   e <  j : X_ie -= f X_je     (A[e][i] -= f A[e][j])
+    //   e == j : X_ij  = -f         (A[j][i]  = -f)
+    //   e >  j : S_ie -= f S_ej     (A[i][e] -= f A[e][j])
+    // Column j is read and never written in step j: one barrier per step.
     for (int j = 0; j < k; ++j) {
-        const double ajj = A[(int64_t)j * k + j];
-        const double inv = ajj > 0.0 ? 1.0 / ajj : 0.0;   // 1 / L_jj^2
-        const int nt = k - 1 - j;
-        const int64_t ntri = (int64_t)nt * (nt + 1) / 2;
-        for (int64_t e = tid; e < ntri; e += nthr) {
-            // e -> (i, l) with j < l <= i < k
-            const int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-            int i0 = ii, l0 = (int)(e - (int64_t)ii * (ii + 1) / 2);
-            if (l0 > i0) { ++i0; l0 = (int)(e - (int64_t)i0 * (i0 + 1) / 2); }
-            if (l0 < 0) { --i0; l0 = (int)(e - (int64_t)i0 * (i0 + 1) / 2); }
-            const int i = j + 1 + i0, l = j + 1 + l0;
-            A[(int64_t)i * k + l] -= A[(int64_t)i * k + j] * A[(int64_t)l * k + j] * inv;
+        const double pj = A[(int64_t)j * k + j];
+        const double inv = pj > 0.0 ? 1.0 / pj : 0.0;
+        for (int i = j + 1 + wave; i < k; i += nw) {
+            const double f = A[(int64_t)i * k + j] * inv;
+            for (int e = lane; e <= i; e += 64) {
+                if (e == j) { A[(int64_t)j * k + i] = -f; continue; }
+                const double v = f * A[(int64_t)e * k + j];
+                if (e < j) A[(int64_t)e * k + i] -= v;
+                else A[(int64_t)i * k + e] -= v;
+            }
         }
-        if (j > 0) {
-            const int jm = j - 1;
-            const double lj = sqrt(fmax(A[(int64_t)jm * k + jm], 0.0));
-            const double li = lj > 0.0 ? 1.0 / lj : 0.0;
-            for (int i = jm + 1 + tid; i < k; i += nthr) A[(int64_t)i * k + jm] *= li;
-        }
-        __syncthreads();
-        if (tid == 0 && j > 0) A[(int64_t)(j - 1) * k + (j - 1)] = sqrt(fmax(A[(int64_t)(j - 1) * k + (j - 1)], 0.0));
         __syncthreads();
     }
-    {
-        const int jm = k - 1;
-        if (tid == 0) A[(int64_t)jm * k + jm] = sqrt(fmax(A[(int64_t)jm * k + jm], 0.0));
-        __syncthreads();
-    }
-    // L^-1 by columns: thread c solves L x = e_c, x_i stored at A[c][i] (i > c)
-    for (int c = tid; c < k; c += nthr) {
-        const double lcc = A[(int64_t)c * k + c];
-        const double xc = lcc > 0.0 ? 1.0 / lcc : 0.0;
-        dinv[c] = xc;
-        for (int i = c + 1; i < k; ++i) {
-            double sacc = A[(int64_t)i * k + c] * xc;
-            for (int jj = c + 1; jj < i; ++jj) sacc += A[(int64_t)i * k + jj] * A[(int64_t)c * k + jj];
-            const double lii = A[(int64_t)i * k + i];
-            A[(int64_t)c * k + i] = lii > 0.0 ? -sacc / lii : 0.0;
-        }
+    for (int i = tid; i < k; i += nthr) {
+        const double p = A[(int64_t)i * k + i];
+        dinv[i] = p > 0.0 ? 1.0 / sqrt(p) : 0.0;
     }
     __syncthreads();
-    // T[i][c] = (L^-1)[i][c] d_c
+    // T[i][c] = p_i^-1/2 X_ic d_c  (X_ii = 1)
     for (int64_t e = tid; e < (int64_t)k * k; e += nthr) {
         const int i = (int)(e / k), c = (int)(e % k);
         double v = 0.0;
-        if (i == c) v = dinv[c];
-        else if (i > c) v = A[(int64_t)c * k + i];
-        jb.T[e] = v * dsc[c];
+        if (i == c) v = dinv[i] * dsc[c];
+        else if (i > c) v = dinv[i] * A[(int64_t)c * k + i] * dsc[c];
+        jb.T[e] = v;
     }
 }
 
@@ -785,11 +867,16 @@ void cholqr(hipStream_t s, const CholBatch& jobs, double shift)
 {
     if (jobs.n <= 0) return;
     int64_t need = 0;
+    bool fits = true;
     for (int i = 0; i < jobs.n; ++i) {
         const int64_t kk = jobs.job[i].k;
-        if (kk * kk + 2 * kk <= kJacobiLdsDoubles && kk * kk + 2 * kk > need) need = kk * kk + 2 * kk;
+        fits = fits && kk * kk + 2 * kk <= kCholLdsDoubles;
+        need = std::max(need, kk * kk + 2 * kk);
     }
-    hipLaunchKernelGGL(cholqr_kernel, dim3(jobs.n), dim3(1024), need * sizeof(double), s, jobs, shift);
+    if (fits)
+        hipLaunchKernelGGL((cholqr_kernel<true>), dim3(jobs.n), dim3(1024), need * sizeof(double), s, jobs, shift);
+    else
+        hipLaunchKernelGGL((cholqr_kernel<false>), dim3(jobs.n), dim3(1024), 0, s, jobs, shift);
 }
 
 }  // namespace ctmk

@@ -1,5 +1,5 @@
 // Test-only C entry points that run single kernels of the library on host
-// buffers (GEMM, permute, Jacobi SVD), so that kernel-level numerics can be
+// buffers (GEMM, Jacobi SVD, Cholesky QR factor), so that kernel-level numerics can be
 // checked in isolation.  Built into libctm_selftest.so, not into libctm.so.
 #include <hip/hip_runtime.h>
 
@@ -18,35 +18,69 @@ T* dev_copy(const T* h, size_t n)
 
 extern "C" {
 
-// C[batch][M][N] = op(A) op(B), all row-major, host buffers
+// C[batch][M][N] = op(A) op(B), all row-major, host buffers.  ws_cap > 0
+// gives the GEMM a split-K workspace of that many doubles.
 int ctm_selftest_gemm(int ta, int tb, int M, int N, int K, int batch, const double* A,
-                      const double* B, double* C)
+                      const double* B, double* C, long long ws_cap)
 {
     const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
     double *dA = dev_copy(A, na), *dB = dev_copy(B, nb), *dC = dev_copy<double>(nullptr, nc);
-    if (!dA || !dB || !dC) return 1;
+    double* dW = ws_cap > 0 ? dev_copy<double>(nullptr, (size_t)ws_cap) : nullptr;
+    if (!dA || !dB || !dC || (ws_cap > 0 && !dW)) return 1;
     ctmk::gemm_f64(nullptr, ta != 0, tb != 0, M, N, K, 1.0, dA, ta ? M : K, (int64_t)M * K, dB,
-                   tb ? K : N, (int64_t)K * N, 0.0, dC, N, (int64_t)M * N, batch);
+                   tb ? K : N, (int64_t)K * N, 0.0, dC, N, (int64_t)M * N, batch, dW, ws_cap);
     int rc = hipMemcpy(C, dC, nc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
     rc |= hipDeviceSynchronize() != hipSuccess;
     (void)hipFree(dA);
     (void)hipFree(dB);
     (void)hipFree(dC);
+    if (dW) (void)hipFree(dW);
     return rc;
 }
 
-// X (m x n column-major) = U S V^T
-int ctm_selftest_jacobi(int m, int n, const double* X, double* U, double* S, double* V)
+// number of K slices gemm_f64 uses for this shape and workspace
+int ctm_selftest_gemm_splits(int M, int N, int K, int batch, long long ws_cap)
 {
+    return ctmk::gemm_split_plan(M, N, K, batch, ws_cap);
+}
+
+// T = L^-1 D for G (k x k, row-major Gram matrix): D = diag(G)^-1/2,
+// L L^T = D G D + shift I
+int ctm_selftest_cholqr(int k, const double* G, double shift, double* T)
+{
+    double *dG = dev_copy(G, (size_t)k * k), *dT = dev_copy<double>(nullptr, (size_t)k * k);
+    double* dw = dev_copy<double>(nullptr, (size_t)2 * k);
+    if (!dG || !dT || !dw) return 1;
+    ctmk::CholBatch cb{};
+    cb.n = 1;
+    cb.job[0] = ctmk::CholJob{dG, dw, dT, k};
+    ctmk::cholqr(nullptr, cb, shift);
+    int rc = hipDeviceSynchronize() != hipSuccess;
+    rc |= hipMemcpy(T, dT, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
+    (void)hipFree(dG);
+    (void)hipFree(dT);
+    (void)hipFree(dw);
+    return rc;
+}
+
+// X (m x n column-major) = U S V^T; *sweeps (may be NULL) receives the sweeps done
+int ctm_selftest_jacobi(int m, int n, const double* X, double* U, double* S, double* V, int* sweeps)
+{
+    int* dsw = dev_copy<int>(nullptr, 1);
+    if (!dsw) return 1;
     double *dX = dev_copy(X, (size_t)m * n), *dW = dev_copy<double>(nullptr, (size_t)n * n);
     double *dU = dev_copy<double>(nullptr, (size_t)m * n), *dV = dev_copy<double>(nullptr, (size_t)n * n);
     double* dS = dev_copy<double>(nullptr, n);
     if (!dX || !dW || !dU || !dV || !dS) return 1;
     ctmk::JacobiBatch jb{};
     jb.n = 1;
-    jb.job[0] = ctmk::JacobiJob{dX, dW, dU, dV, dS, m, n, 1};
+    jb.job[0] = ctmk::JacobiJob{dX, dW, dU, dV, dS, m, n, 1, dsw};
     ctmk::jacobi_svd(nullptr, jb, 40);
     int rc = hipDeviceSynchronize() != hipSuccess;
+    int sw = 0;
+    rc |= hipMemcpy(&sw, dsw, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess;
+    if (sweeps) *sweeps = sw;
+    (void)hipFree(dsw);
     rc |= hipMemcpy(U, dU, (size_t)m * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
     rc |= hipMemcpy(V, dV, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
     rc |= hipMemcpy(S, dS, (size_t)n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;

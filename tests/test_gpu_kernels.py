@@ -1,5 +1,6 @@
-"""Kernel-level numerics of the HIP library on the GPU: the FP64 MFMA GEMM and
-the one-sided Jacobi SVD, against NumPy on the same inputs."""
+"""Kernel-level numerics of the HIP library on the GPU: the FP64 MFMA GEMM
+(single pass and split-K), the one-sided Jacobi SVD and the shifted Cholesky QR
+factor, against NumPy on the same inputs."""
 import ctypes
 import os
 
@@ -18,8 +19,10 @@ def lib():
         raise OSError("libctm_selftest.so is not built")
     L = ctypes.CDLL(SELFTEST)
     dp = ctypes.POINTER(ctypes.c_double)
-    L.ctm_selftest_gemm.argtypes = [ctypes.c_int] * 6 + [dp, dp, dp]
-    L.ctm_selftest_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
+    L.ctm_selftest_gemm.argtypes = [ctypes.c_int] * 6 + [dp, dp, dp, ctypes.c_longlong]
+    L.ctm_selftest_gemm_splits.argtypes = [ctypes.c_int] * 4 + [ctypes.c_longlong]
+    L.ctm_selftest_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    L.ctm_selftest_cholqr.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
     return L
 
 
@@ -31,13 +34,64 @@ def _p(a):
 @pytest.mark.parametrize("M,N,K,batch", [(1, 1, 1, 1), (16, 16, 4, 1), (65, 130, 17, 1),
                                          (200, 37, 300, 3), (5, 64, 1, 2), (1000, 100, 1000, 1)])
 def test_gemm_matches_numpy(lib, ta, tb, M, N, K, batch):
+    _gemm_case(lib, ta, tb, M, N, K, batch, 0)
+
+
+def _gemm_case(lib, ta, tb, M, N, K, batch, ws_cap):
     rng = np.random.default_rng(M * 7 + N + K)
     A = rng.standard_normal((batch, K, M) if ta else (batch, M, K))
     B = rng.standard_normal((batch, N, K) if tb else (batch, K, N))
     C = np.zeros((batch, M, N))
-    assert lib.ctm_selftest_gemm(ta, tb, M, N, K, batch, _p(A), _p(B), _p(C)) == 0
+    assert lib.ctm_selftest_gemm(ta, tb, M, N, K, batch, _p(A), _p(B), _p(C), ws_cap) == 0
     ref = np.matmul(A.transpose(0, 2, 1) if ta else A, B.transpose(0, 2, 1) if tb else B)
-    assert np.max(np.abs(C - ref)) <= 1e-13 * max(1.0, K) * np.max(np.abs(ref)) + 1e-300
+    # FP64 dot products of length K: |error| <= K eps sum|a||b| ~ K eps sqrt(K) for N(0,1) data
+    assert np.max(np.abs(C - ref)) <= 4e-16 * K * np.sqrt(K) + 1e-300
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("M,N,K,batch", [(135, 135, 1000, 1), (135, 1000, 1000, 1), (7, 9, 333, 3),
+                                         (64, 64, 4096, 1), (100, 3, 257, 2)])
+def test_gemm_split_k_matches_numpy(lib, ta, tb, M, N, K, batch):
+    cap = 1 << 22
+    assert lib.ctm_selftest_gemm_splits(M, N, K, batch, cap) > 1
+    _gemm_case(lib, ta, tb, M, N, K, batch, cap)
+
+
+@pytest.mark.parametrize("k,rank", [(1, 1), (16, 16), (100, 100), (135, 135), (135, 90), (141, 141), (160, 160)])
+def test_cholqr_factor(lib, k, rank):
+    """T = L^-1 D with L L^T = D G D + shift I, T lower triangular (k = 160
+    takes the global-memory path).  Full rank: T matches LAPACK's factor.
+    Rank deficient: the factor is as ill-conditioned as 1/shift, so what is
+    checked is the property the subspace iteration needs, that two passes
+    give orthonormal rows."""
+    rng = np.random.default_rng(k + rank)
+    Y = rng.standard_normal((k, 3 * k))
+    if rank < k:
+        Y[rank:] = rng.standard_normal((k - rank, rank)) @ Y[:rank] * 1e-3
+    Y *= np.logspace(0, -6, k)[:, None]
+    shift = 1e-14
+
+    def factor(Yr):
+        G = np.ascontiguousarray(Yr @ Yr.T)
+        T = np.zeros((k, k))
+        assert lib.ctm_selftest_cholqr(k, _p(G), shift, _p(T)) == 0
+        assert np.all(np.triu(T, 1) == 0.0)
+        return G, T
+
+    G, T = factor(Y)
+    if rank == k:
+        d = 1.0 / np.sqrt(np.diag(G))
+        L = np.linalg.cholesky(d[:, None] * G * d[None, :] + shift * np.eye(k))
+        ref = np.linalg.solve(L, np.diag(d))
+        scale = np.abs(ref).max(axis=1, keepdims=True)
+        assert np.max(np.abs(T - ref) / scale) <= 1e-12
+        Q = T @ Y
+        assert np.max(np.abs(Q @ Q.T - np.eye(k))) <= 1e-9
+    else:
+        Q1 = T @ Y
+        _, T2 = factor(Q1)
+        Q2 = T2 @ Q1
+        assert np.max(np.abs(Q2 @ Q2.T - np.eye(k))) <= 1e-9
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (8, 8), (33, 17), (64, 64), (100, 100), (300, 120), (256, 256)])
@@ -52,7 +106,10 @@ def test_jacobi_svd_matches_numpy(lib, m, n):
     U = np.zeros((n, m))
     V = np.zeros((n, n))
     S = np.zeros(n)
-    assert lib.ctm_selftest_jacobi(m, n, _p(Xcm.ravel(order="F").copy()), _p(U), _p(S), _p(V)) == 0
+    sweeps = ctypes.c_int(0)
+    assert lib.ctm_selftest_jacobi(m, n, _p(Xcm.ravel(order="F").copy()), _p(U), _p(S), _p(V),
+                                   ctypes.byref(sweeps)) == 0
+    assert 1 <= sweeps.value < 40, sweeps.value
     U = U.T   # columns
     V = V.T
     k = min(m, n)

@@ -4,7 +4,11 @@ same truncation rule), through the C ABI.
 Tolerances (FP64 on both sides; the oracle uses LAPACK SVDs, the GPU its own
 Jacobi / subspace SVD): after the iteration has converged the two agree to
 rounding, amplified by the projectors' S^-1/2; we require 1e-10 relative on f,
-1e-8 relative (l2) on g and 1e-10 absolute on the normalised spectrum.
+1e-8 relative (l2) on g and 1e-9 absolute on the normalised spectrum.  The
+spectrum (the convergence measure of Sec. III D) is the least well conditioned
+of these outputs: at beta = 0.22, D = 3, chi = 20 the oracle's own spectrum
+moves by ~7e-11 when A is perturbed by 1e-15 relative, while ln kappa moves by
+~1e-12.
 """
 import numpy as np
 import pytest
@@ -48,7 +52,7 @@ def compare(got, ref):
         n = max(len(s), len(so))
         a, b = np.zeros(n), np.zeros(n)
         a[: len(s)], b[: len(so)] = s, so
-        assert np.max(np.abs(a - b)) <= 1e-10
+        assert np.max(np.abs(a - b)) <= 1e-9
 
 
 def test_d2_chi16_forty_iterations():
