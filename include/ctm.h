@@ -26,11 +26,14 @@
  * cfg->flags has CTM_FLAG_DEVICE_PTRS set, in which case A and g are device
  * pointers on the current HIP device.
  *
- * Streams.  All device work of a context is enqueued on the hip_stream given at
- * init (NULL = the legacy default stream).  Calls that return host values
- * (ctm_iterate's delta, ctm_free_energy, ctm_grad with host g, spectra)
- * synchronise that stream.  A context must be used by one host thread at a
- * time; distinct contexts are independent.
+ * Streams.  The work of every call is ordered after the work already
+ * enqueued on the hip_stream given at init (NULL = the legacy default stream),
+ * and work enqueued on that stream after the call returns is ordered after
+ * it.  Inside a call the two networks run concurrently on two streams the
+ * context owns (default priority), each driven by its own host thread.  Calls
+ * that return host values (ctm_iterate's delta, ctm_free_energy, ctm_grad
+ * with host g, spectra) synchronise.  A context must be used by one host
+ * thread at a time; distinct contexts are independent.
  *
  * Errors.  Every call returns a ctm_status; nothing is thrown across the ABI.
  * ctm_last_error() gives a message for the last failing call on a context.

@@ -36,7 +36,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <stdexcept>
+#include <exception>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ctm.h"
@@ -174,30 +176,64 @@ constexpr int64_t kCoreMax = 135;   // largest k x k factorisation held in LDS
 // it resolves in FP64.
 constexpr double kDefaultCutoff = 1e-8;
 constexpr int kJacobiSweeps = 40;
+constexpr int kMaxBatch = 16;       // projectors factorised together
 
 }  // namespace
 
-struct ctm_ctx {
+// ---------------------------------------------------------------------------
+// one worker per network: its own stream, workspace arena, scratch and launch
+// statistics, so that the triple- and double-layer networks (independent until
+// f is formed) run concurrently, each from its own host thread.
+// ---------------------------------------------------------------------------
+struct Worker {
     ctm_config cfg{};
-    double beta = 0.0;
-    int D = 0, chi = 0, xmax = 0;
-    hipStream_t st = nullptr;
-    int device = 0;
+    int D = 0;
+    const double* A = nullptr;       // D4-projected A, owned by the context
+    hipStream_t st = nullptr;        // created by the context (default priority)
     Arena ws;
-    std::vector<void*> owned;        // persistent allocations
-    double* A = nullptr;             // D4-projected A, [2][D][D][D][D]
+    std::vector<void*> owned;        // persistent allocations of this worker
     double* part = nullptr;          // reduction partials
     double* scal = nullptr;          // scratch scalars
-    int* icount = nullptr;           // device int for rank read-back
+    int* icount = nullptr;           // device ints for rank read-back
     double* gws = nullptr;           // split-K partial products of the GEMMs
     int64_t gws_cap = 0;
-    Net net[2];                      // [0] triple, [1] double
-    int iters = 0;
     uint64_t svd_calls = 0;
     int64_t exact_min = kJacobiExact, exact_area = kJacobiExactArea;
     bool profiling = false;
     KStat kstat[3];                  // [0] GEMM (MFMA), [1] Jacobi SVD, [2] Cholesky QR
     std::vector<hipEvent_t> ev_pool;
+
+    void setup(const ctm_config& c, int d_bond, const double* a)
+    {
+        cfg = c;
+        D = d_bond;
+        A = a;
+        profiling = (c.flags & CTM_FLAG_PROFILE) != 0;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        part = keep(ctmk::kRedBlocks);
+        scal = keep(16);
+        icount = (int*)keep(kMaxBatch);
+        gws_cap = (int64_t)1 << 22;   // 32 MiB
+        gws = keep(gws_cap);
+    }
+    void release()
+    {
+        if (st) (void)hipStreamSynchronize(st);
+        ws.free_all();
+        for (void* p : owned) (void)hipFree(p);
+        owned.clear();
+        for (auto& k : kstat) {
+            for (auto& pr : k.pending) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+            k.pending.clear();
+        }
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        ev_pool.clear();
+        if (st) (void)hipStreamDestroy(st);
+        st = nullptr;
+    }
 
     hipEvent_t ev_get()
     {
@@ -249,9 +285,6 @@ struct ctm_ctx {
                        gws, gws_cap);
         prof_end(0, e, 2.0 * (double)M * (double)N * (double)K * (double)nb);
     }
-    struct Warm { double* V = nullptr; int64_t cap = 0, n = 0, k = 0; };
-    Warm warm[12];                   // per projector slot (network x P1..P6)
-    std::string err;
 
     // ---------------- allocation helpers
     double* keep(int64_t count)
@@ -408,141 +441,222 @@ struct ctm_ctx {
         return C;
     }
 
-    // Jacobi SVD of X given as an m x n column-major matrix (n columns).
-    // Returns U (m x n col-major), V (n x n col-major), S (n): X = U S V^T.
-    void jacobi(const Tn& Xcm, int64_t m, int64_t n, Tn& U, Tn& V, Tn& S, bool want_v = true)
+    // ---------------- batched factorisations
+    // One-sided Jacobi SVDs of matrices given column-major (m rows, n columns),
+    // all problems of the list in one launch per group of kMaxJacobiBatch:
+    // X = U S V^T with U (n x m: row j = column j), V (n x n), S (n, descending).
+    struct JReq {
+        const double* X;
+        int64_t m, n;
+        bool want_v;
+        Tn U, V, S;
+    };
+    void jacobi_batch(std::vector<JReq>& rq)
     {
-        REQUIRE(n <= 1024, "Jacobi: too many columns");
-        Tn X = tmp({n, m});
-        ctmk::copy(st, Xcm.p, X.p, m * n);
-        Tn W = tmp({n, n});
-        U = tmp({n, m});
-        V = tmp({n, n});
-        S = tmp({n});
-        ctmk::JacobiBatch jb{};
-        jb.n = 1;
-        jb.job[0] = ctmk::JacobiJob{X.p, W.p, U.p, V.p, S.p, (int)m, (int)n, want_v ? 1 : 0, nullptr};
-        hipEvent_t e = prof_begin();
-        ctmk::jacobi_svd(st, jb, kJacobiSweeps);
-        prof_end(1, e, 0.0);
+        for (size_t b0 = 0; b0 < rq.size(); b0 += ctmk::kMaxJacobiBatch) {
+            ctmk::JacobiBatch jb{};
+            const size_t b1 = std::min(rq.size(), b0 + (size_t)ctmk::kMaxJacobiBatch);
+            for (size_t i = b0; i < b1; ++i) {
+                JReq& r = rq[i];
+                REQUIRE(r.n <= 1024, "Jacobi: too many columns");
+                Tn X = tmp({r.n, r.m});
+                ctmk::copy(st, r.X, X.p, r.m * r.n);
+                Tn W = tmp({r.n, r.n});
+                r.U = tmp({r.n, r.m});
+                r.V = tmp({r.n, r.n});
+                r.S = tmp({r.n});
+                jb.job[jb.n++] = ctmk::JacobiJob{X.p, W.p, r.U.p, r.V.p, r.S.p, (int)r.m, (int)r.n,
+                                                 r.want_v ? 1 : 0, nullptr};
+            }
+            hipEvent_t e = prof_begin();
+            ctmk::jacobi_svd(st, jb, kJacobiSweeps);
+            prof_end(1, e, 0.0);
+        }
     }
 
-    // one shifted Cholesky QR pass on the rows of Yt (k x L): G = Yt Yt^T,
-    // T = L^-1 D with L L^T = D G D + shift I, D = diag(G)^-1/2; returns T Yt.
-    Tn cholqr_pass(const Tn& Yt)
+    // one shifted Cholesky QR pass on the rows of every Y (k x L) of the list:
+    // G = Y Y^T, T = L^-1 D with L L^T = D G D + shift I, D = diag(G)^-1/2;
+    // Y <- T Y.  The factors of all problems are built in one launch.
+    void cholqr_pass(std::vector<Tn>& Ys)
     {
-        const int64_t k = Yt.d[0];
-        Tn G = mm(Yt, false, Yt, true);
-        Tn T = tmp({k, k});
-        Tn work = tmp({2 * k});
-        ctmk::CholBatch cb{};
-        cb.n = 1;
-        cb.job[0] = ctmk::CholJob{G.p, work.p, T.p, (int)k};
-        hipEvent_t e = prof_begin();
-        ctmk::cholqr(st, cb, 1e-14);
-        prof_end(2, e, 0.0);
-        return mm(T, false, Yt, false);
+        std::vector<Tn> Ts(Ys.size());
+        for (size_t b0 = 0; b0 < Ys.size(); b0 += ctmk::kMaxJacobiBatch) {
+            const size_t b1 = std::min(Ys.size(), b0 + (size_t)ctmk::kMaxJacobiBatch);
+            ctmk::CholBatch cb{};
+            for (size_t i = b0; i < b1; ++i) {
+                const int64_t k = Ys[i].d[0];
+                Tn G = mm(Ys[i], false, Ys[i], true);
+                Ts[i] = tmp({k, k});
+                Tn work = tmp({2 * k});
+                cb.job[cb.n++] = ctmk::CholJob{G.p, work.p, Ts[i].p, (int)k};
+            }
+            hipEvent_t e = prof_begin();
+            ctmk::cholqr(st, cb, 1e-14);
+            prof_end(2, e, 0.0);
+        }
+        for (size_t i = 0; i < Ys.size(); ++i) Ys[i] = mm(Ts[i], false, Ys[i], false);
     }
 
-    // rows of Yt -> orthonormal rows spanning the same space (shifted
+    // rows of every Y -> orthonormal rows spanning the same space (shifted
     // Cholesky QR, twice).  Small directions are kept (the shift bounds their
     // amplification) so that the power steps can refine them.
-    Tn orth(const Tn& Yt) { return cholqr_pass(cholqr_pass(Yt)); }
-
-    // top-kk singular triplets of M (m x n row-major): UT (kk x m), S (kk), VT (kk x n).
-    // min(m, n) <= kJacobiExact: exact one-sided Jacobi SVD.  Otherwise block
-    // subspace iteration on M^T M (k vectors, k >= kk + oversampling) started
-    // from counter-based normals, followed by a Rayleigh-Ritz step whose small
-    // core (Q^T M P) is factorised by Jacobi.
-    void svd_topk(const Tn& M, int64_t kk, int slot, Tn& UT, Tn& S, Tn& VT)
+    void orth(std::vector<Tn>& Ys)
     {
-        const int64_t m = M.d[0], n = M.d[1], mn = std::min(m, n);
-        Tn U, V, Sv;
-        if (mn <= exact_min || m * n <= exact_area) {
-            if (m <= n) {
-                // M row-major == M^T column-major (n rows, m columns)
-                jacobi(M, n, m, U, V, Sv);
-                // M = V S U^T : left vectors = columns of V (m), right = columns of U (n)
-                UT = make_tn(V.p, {kk, m});
-                VT = make_tn(U.p, {kk, n});
+        cholqr_pass(Ys);
+        cholqr_pass(Ys);
+    }
+
+    // top-kk singular triplets of each M (m x n row-major): UT (kk x m), S (kk),
+    // VT (kk x n).  min(m, n) <= exact_min or m n <= exact_area: exact one-sided
+    // Jacobi SVD.  Otherwise block subspace iteration on M^T M (k vectors,
+    // k >= kk + oversampling) from counter-based normals, and a Rayleigh-Ritz
+    // step whose small core Q^T M P is factorised by Jacobi.  All problems of
+    // the list advance together so that every factorisation kernel serves all
+    // of them in one launch.
+    struct SvdReq {
+        Tn M;
+        int64_t kk;
+        Tn UT, S, VT;
+    };
+    void svd_batch(std::vector<SvdReq>& rq)
+    {
+        std::vector<JReq> ex;
+        std::vector<size_t> ex_of, rnd;
+        std::vector<bool> ex_t;
+        for (size_t i = 0; i < rq.size(); ++i) {
+            const Tn& M = rq[i].M;
+            const int64_t m = M.d[0], n = M.d[1], mn = std::min(m, n);
+            if (mn <= exact_min || m * n <= exact_area) {
+                if (m <= n) {
+                    // M row-major == M^T column-major (n rows, m columns)
+                    ex.push_back(JReq{M.p, n, m, true, {}, {}, {}});
+                    ex_t.push_back(false);
+                } else {
+                    Tn Mt = perm(M, "ab->ba");   // M column-major: m rows, n columns
+                    ex.push_back(JReq{Mt.p, m, n, true, {}, {}, {}});
+                    ex_t.push_back(true);
+                }
+                ex_of.push_back(i);
             } else {
-                Tn Mt = perm(M, "ab->ba");   // M^T row-major == M column-major (m rows, n cols)
-                jacobi(Mt, m, n, U, V, Sv);
-                UT = make_tn(U.p, {kk, m});
-                VT = make_tn(V.p, {kk, n});
+                rnd.push_back(i);
             }
-            S = make_tn(Sv.p, {kk});
-            return;
         }
+        jacobi_batch(ex);
+        for (size_t e = 0; e < ex.size(); ++e) {
+            SvdReq& r = rq[ex_of[e]];
+            const int64_t m = r.M.d[0], n = r.M.d[1];
+            if (!ex_t[e]) {
+                // M^T = U S V^T -> M = V S U^T: left vectors = rows of V, right = rows of U
+                r.UT = make_tn(ex[e].V.p, {r.kk, m});
+                r.VT = make_tn(ex[e].U.p, {r.kk, n});
+            } else {
+                r.UT = make_tn(ex[e].U.p, {r.kk, m});
+                r.VT = make_tn(ex[e].V.p, {r.kk, n});
+            }
+            r.S = make_tn(ex[e].S.p, {r.kk});
+        }
+        if (rnd.empty()) return;
         // oversampling: near the cut the spectra of these environments are
         // flat (sigma_{1.16 chi} / sigma_chi ~ 0.5), so the subspace extends
         // to min(2 kk, 135) vectors (the largest core that stays in LDS) and
         // six power steps resolve the kept directions to ~1e-10.  The bond
         // gauge changes every iteration, so the previous subspace is no better
         // a start than a random one.
-        const int64_t k = std::min<int64_t>(std::max<int64_t>(std::min<int64_t>(2 * kk, kCoreMax), kk + kOversample), mn);
-        Tn Pt = tmp({k, n});
-        (void)slot;
-        ctmk::randn(st, Pt.p, k * n, 0x5eedull + 7919ull * (++svd_calls));
-        const int q = cfg.power_iters > 0 ? cfg.power_iters : 6;
-        Pt = orth(Pt);
-        for (int it = 0; it < q; ++it) {
-            Tn Yt = mm(Pt, false, M, true);       // (M P)^T
-            Tn Qt = orth(Yt);
-            Tn Zt = mm(Qt, false, M, false);      // (M^T Q)^T
-            Pt = orth(Zt);
+        const size_t nr = rnd.size();
+        std::vector<Tn> Pt(nr), Qt(nr);
+        for (size_t j = 0; j < nr; ++j) {
+            const SvdReq& r = rq[rnd[j]];
+            const int64_t m = r.M.d[0], n = r.M.d[1], mn = std::min(m, n);
+            const int64_t k = std::min<int64_t>(
+                std::max<int64_t>(std::min<int64_t>(2 * r.kk, kCoreMax), r.kk + kOversample), mn);
+            Pt[j] = tmp({k, n});
+            ctmk::randn(st, Pt[j].p, k * n, 0x5eedull + 7919ull * (++svd_calls));
         }
-        Tn Yt = mm(Pt, false, M, true);
-        Tn Qt = orth(Yt);
-        Tn X1 = mm(Qt, false, M, false);          // Q^T M   (k x n)
-        Tn Bs = mm(X1, false, Pt, true);          // Q^T M P (k x k)
-        // Bs row-major == Bs^T col-major: Bs^T = Uj S Vj^T -> Bs = Vj S Uj^T
-        jacobi(Bs, k, k, U, V, Sv);
-        Tn Vjt = make_tn(V.p, {k, k});            // rows = left vectors of Bs
-        Tn Ujt = make_tn(U.p, {k, k});            // rows = right vectors of Bs
-        Tn UTf = mm(Vjt, false, Qt, false);       // (Q Us)^T
-        Tn VTf = mm(Ujt, false, Pt, false);       // (P Vs)^T
-        UT = make_tn(UTf.p, {kk, m});
-        VT = make_tn(VTf.p, {kk, n});
-        S = make_tn(Sv.p, {kk});
+        const int q = cfg.power_iters > 0 ? cfg.power_iters : 6;
+        orth(Pt);
+        for (int it = 0; it < q; ++it) {
+            for (size_t j = 0; j < nr; ++j) Qt[j] = mm(Pt[j], false, rq[rnd[j]].M, true);   // (M P)^T
+            orth(Qt);
+            for (size_t j = 0; j < nr; ++j) Pt[j] = mm(Qt[j], false, rq[rnd[j]].M, false);  // (M^T Q)^T
+            orth(Pt);
+        }
+        for (size_t j = 0; j < nr; ++j) Qt[j] = mm(Pt[j], false, rq[rnd[j]].M, true);
+        orth(Qt);
+        std::vector<JReq> core(nr);
+        for (size_t j = 0; j < nr; ++j) {
+            Tn X1 = mm(Qt[j], false, rq[rnd[j]].M, false);   // Q^T M   (k x n)
+            Tn Bs = mm(X1, false, Pt[j], true);               // Q^T M P (k x k)
+            const int64_t k = Bs.d[0];
+            // Bs row-major == Bs^T col-major: Bs^T = Uj S Vj^T -> Bs = Vj S Uj^T
+            core[j] = JReq{Bs.p, k, k, true, {}, {}, {}};
+        }
+        jacobi_batch(core);
+        for (size_t j = 0; j < nr; ++j) {
+            SvdReq& r = rq[rnd[j]];
+            const int64_t m = r.M.d[0], n = r.M.d[1], k = core[j].S.d[0];
+            Tn Vjt = make_tn(core[j].V.p, {k, k});   // rows = left vectors of Bs
+            Tn Ujt = make_tn(core[j].U.p, {k, k});   // rows = right vectors of Bs
+            Tn UTf = mm(Vjt, false, Qt[j], false);   // (Q Us)^T
+            Tn VTf = mm(Ujt, false, Pt[j], false);   // (P Vs)^T
+            r.UT = make_tn(UTf.p, {r.kk, m});
+            r.VT = make_tn(VTf.p, {r.kk, n});
+            r.S = make_tn(core[j].S.p, {r.kk});
+        }
     }
 
-    // projector pair from rhoT (t x rT) and rhoB (rB x t)
-    Projector projector(const Tn& rT, const Tn& rB, int64_t chi, int slot)
+    // projector pairs from (rhoT (t x rT), rhoB (rB x t)) for every entry of
+    // the list; the factorisations of all entries share their launches and one
+    // read-back of the kept ranks.
+    std::vector<Projector> projectors(const std::vector<std::pair<Tn, Tn>>& prs, int64_t chi)
     {
-        const int64_t t = rT.d[0], remT = rT.d[1], remB = rB.d[0];
-        REQUIRE(rT.r == 2 && rB.r == 2 && rB.d[1] == t, "projector shapes");
-        Projector P;
-        if (t <= chi) {
-            Tn I = tmp({t, t});
-            ctmk::eye(st, I.p, (int)t);
-            P.PT = I;
-            P.PB = I;
-            P.k = (int)t;
-            return P;
+        REQUIRE(prs.size() <= (size_t)kMaxBatch, "too many projectors in one batch");
+        std::vector<Projector> out(prs.size());
+        std::vector<SvdReq> rq;
+        std::vector<size_t> of;
+        for (size_t i = 0; i < prs.size(); ++i) {
+            const Tn &rT = prs[i].first, &rB = prs[i].second;
+            const int64_t t = rT.d[0], remT = rT.d[1], remB = rB.d[0];
+            REQUIRE(rT.r == 2 && rB.r == 2 && rB.d[1] == t, "projector shapes");
+            if (t <= chi) {
+                Tn I = tmp({t, t});
+                ctmk::eye(st, I.p, (int)t);
+                out[i].PT = I;
+                out[i].PB = I;
+                out[i].k = (int)t;
+                continue;
+            }
+            SvdReq r;
+            r.M = mm(rB, false, rT, false);          // remB x remT
+            r.kk = std::min<int64_t>(chi, std::min(remB, remT));
+            rq.push_back(r);
+            of.push_back(i);
         }
-        Tn M = mm(rB, false, rT, false);          // remB x remT
-        const int64_t k0 = std::min<int64_t>(chi, std::min(remB, remT));
-        Tn UT, S, VT;
-        svd_topk(M, k0, slot, UT, S, VT);
-        // the bond keeps the chi largest singular values that are above the
-        // relative cutoff (its numerical rank): one small read-back
+        if (rq.empty()) return out;
+        svd_batch(rq);
+        // each bond keeps the chi largest singular values that are above the
+        // relative cutoff (its numerical rank): one small read-back for all
         const double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : kDefaultCutoff;
-        ctmk::count_above(st, S.p, (int)k0, cut, icount);
-        int rank = 0;
-        HIPCHK(hipMemcpyAsync(&rank, icount, sizeof(int), hipMemcpyDeviceToHost, st));
+        for (size_t j = 0; j < rq.size(); ++j) ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut, icount + j);
+        int rank[kMaxBatch] = {0};
+        HIPCHK(hipMemcpyAsync(rank, icount, rq.size() * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        const int64_t kk = std::max<int64_t>(1, std::min<int64_t>(k0, rank));
-        UT.d[0] = kk;
-        VT.d[0] = kk;
-        Tn f = tmp({kk});
-        ctmk::inv_sqrt_cut(st, S.p, f.p, (int)kk, cut);
-        P.PB = mm(rT, false, VT, true);           // t x kk
-        ctmk::scale_lines(st, P.PB.p, (int)t, (int)kk, f.p, 1);
-        P.PT = mm(UT, false, rB, false);          // kk x t
-        ctmk::scale_lines(st, P.PT.p, (int)kk, (int)t, f.p, 0);
-        P.k = (int)kk;
-        return P;
+        for (size_t j = 0; j < rq.size(); ++j) {
+            const size_t i = of[j];
+            const Tn &rT = prs[i].first, &rB = prs[i].second;
+            const int64_t t = rT.d[0];
+            const int64_t kk = std::max<int64_t>(1, std::min<int64_t>(rq[j].kk, rank[j]));
+            Tn UT = rq[j].UT, VT = rq[j].VT;
+            UT.d[0] = kk;
+            VT.d[0] = kk;
+            Tn f = tmp({kk});
+            ctmk::inv_sqrt_cut(st, rq[j].S.p, f.p, (int)kk, cut);
+            out[i].PB = mm(rT, false, VT, true);           // t x kk
+            ctmk::scale_lines(st, out[i].PB.p, (int)t, (int)kk, f.p, 1);
+            out[i].PT = mm(UT, false, rB, false);          // kk x t
+            ctmk::scale_lines(st, out[i].PT.p, (int)kk, (int)t, f.p, 0);
+            out[i].k = (int)kk;
+        }
+        return out;
     }
 
     void normalize(Tn& X)
@@ -552,23 +666,22 @@ struct ctm_ctx {
     }
 
     // ---------------- one symmetric split-CTMRG iteration of one network
-    void step(Net& N, int64_t chi, int net_id);
-    void values(Net& N, double* sc_out, bool with_env);
+    void step(Net& N, int64_t chi);
+    void values(Net& N, bool with_env);
 };
 
 // --------------------------------------------------------------------------
 // the iteration
 // --------------------------------------------------------------------------
-void ctm_ctx::step(Net& N, int64_t chi, int net_id)
+void Worker::step(Net& N, int64_t chi)
 {
-    const int sl = 6 * net_id;
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
     Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
     Tn K = make_tn(N.Tk, {N.xbk, D, N.xki});
     Tn I = make_tn(N.Ti, {N.xki, d, N.xib});
     Tn Bt = make_tn(N.Tb, {N.xib, D, N.xbk});
-    Tn A = make_tn(this->A, {P, D, D, D, D});
+    Tn A = make_tn(const_cast<double*>(this->A), {P, D, D, D, D});
     Tn O = make_tn(N.O, {P, P, d, d, d, d});
     // right / bottom edge chain (D2 relations)
     Tn Rk = perm(Bt, "bma->amb"), Ri = perm(I, "bma->amb"), Rb = perm(K, "bma->amb");
@@ -592,13 +705,16 @@ void ctm_ctx::step(Net& N, int64_t chi, int net_id)
     const int64_t xbk = N.xbk, xki = N.xki, xib = N.xib;
     Tn rT1 = perm(upbk, "vetnz->ventz");
     Tn rB1 = perm(upbk, "fbcea->bcfae");
-    Projector P1 = projector(view(rT1, {xbk * D, D * d * xbk}), view(rB1, {D * d * xbk, xbk * D}), chi, sl + 0);
     Tn rT2 = perm(upki, "gpnibh->gibnph");
     Tn rB2 = perm(upib, "jqtnbk->bqjktn");
-    Projector P2 = projector(view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D}), chi, sl + 1);
     Tn rT3 = perm(upib, "jqtnbk->jbqntk");
     Tn rB3 = perm(upki, "gpnibh->bighnp");
-    Projector P3 = projector(view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P}), chi, sl + 2);
+    std::vector<Projector> S1 = projectors(
+        {{view(rT1, {xbk * D, D * d * xbk}), view(rB1, {D * d * xbk, xbk * D})},
+         {view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D})},
+         {view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P})}},
+        chi);
+    const Projector &P1 = S1[0], &P2 = S1[1], &P3 = S1[2];
     const int64_t c1 = P1.k, c2 = P2.k, c3 = P3.k;
     Tn P1T = view(P1.PT, {c1, xbk, D}), P1B = view(P1.PB, {xbk, D, c1});
     Tn P2T = view(P2.PT, {c2, xki, d, D}), P2B = view(P2.PB, {xki, d, D, c2});
@@ -631,7 +747,6 @@ void ctm_ctx::step(Net& N, int64_t chi, int net_id)
     // ---- stage 2: half P4 from the two corners
     const int64_t n4 = c1 * D * d;
     Tn rB4 = perm(C4p, "cauXbo->Xbocau");
-    Projector P4 = projector(view(C1p, {n4, n4}), view(rB4, {n4, n4}), chi, sl + 3);
 
     // ---- stage 2: P5 (ki) and P6 (ib) from the two-column block
     Tn L = ctr("ykibf,ylg->kibflg", TRpre, K);
@@ -653,8 +768,12 @@ void ctm_ctx::step(Net& N, int64_t chi, int net_id)
     Tn rT6 = ctr("cfnrst,fbrqsd->cntbqd", UL6, UR6);    // [c3L, Ad1, Od1, Bu2, q2, c3R]
     Tn rB5 = perm(rT6, "gfebca->efgabc");               // rotation image of rho_T6
     Tn rB6 = perm(rT5, "gefcba->efgabc");               // rotation image of rho_T5
-    Projector P5 = projector(view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P}), chi, sl + 4);
-    Projector P6 = projector(view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d}), chi, sl + 5);
+    std::vector<Projector> S2 = projectors(
+        {{view(C1p, {n4, n4}), view(rB4, {n4, n4})},
+         {view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P})},
+         {view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d})}},
+        chi);
+    const Projector &P4 = S2[0], &P5 = S2[1], &P6 = S2[2];
     const int64_t k4 = P4.k, k5 = P5.k, k6 = P6.k;
     Tn P4T = view(P4.PT, {k4, c1, D, d}), P4B = view(P4.PB, {c1, D, d, k4});
     Tn P5T = view(P5.PT, {k5, c2, D, P}), P5B = view(P5.PB, {c2, D, P, k5});
@@ -695,9 +814,9 @@ void ctm_ctx::step(Net& N, int64_t chi, int net_id)
     Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
     Tn R = ctr("ab,bc->ac", R1, R1);
     ctmk::trace(st, R.p, (int)k4, N.sc + 7);
-    Tn Uj, Vj, Sj;
-    jacobi(R, k4, k4, Uj, Vj, Sj);
-    ctmk::spectrum_delta(st, Sj.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
+    std::vector<JReq> sp{JReq{R.p, k4, k4, false, {}, {}, {}}};
+    jacobi_batch(sp);
+    ctmk::spectrum_delta(st, sp[0].S.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
 
     // ---- store
     N.xbk = k4;
@@ -713,7 +832,7 @@ void ctm_ctx::step(Net& N, int64_t chi, int net_id)
 
 // n1, n2h, n2v, n0 into N.sc[0..3], ln kappa into N.sc[4], flag N.sc[5];
 // with_env: also the bra environment into N.E and its overlap with A in N.sc[6]
-void ctm_ctx::values(Net& N, double* /*unused*/, bool with_env)
+void Worker::values(Net& N, bool with_env)
 {
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
@@ -721,7 +840,7 @@ void ctm_ctx::values(Net& N, double* /*unused*/, bool with_env)
     Tn K = make_tn(N.Tk, {N.xbk, D, N.xki});
     Tn I = make_tn(N.Ti, {N.xki, d, N.xib});
     Tn Bt = make_tn(N.Tb, {N.xib, D, N.xbk});
-    Tn A = make_tn(this->A, {P, D, D, D, D});
+    Tn A = make_tn(const_cast<double*>(this->A), {P, D, D, D, D});
     Tn O = make_tn(N.O, {P, P, d, d, d, d});
     Tn Rk = perm(Bt, "bma->amb"), Ri = perm(I, "bma->amb"), Rb = perm(K, "bma->amb");
     Tn H = ctr("xy,xkc->ykc", C1, K);
@@ -767,6 +886,75 @@ void ctm_ctx::values(Net& N, double* /*unused*/, bool with_env)
 }
 
 // ---------------------------------------------------------------------------
+// context: the shared state (A, configuration) and one worker per network
+// ---------------------------------------------------------------------------
+struct ctm_ctx {
+    ctm_config cfg{};
+    double beta = 0.0;
+    int D = 0, chi = 0, xmax = 0;
+    hipStream_t ust = nullptr;       // the caller's stream
+    int device = 0;
+    std::vector<void*> owned;        // persistent allocations
+    double* A = nullptr;             // D4-projected A, [2][D][D][D][D]
+    Net net[2];                      // [0] triple, [1] double
+    Worker w[2];                     // one per network
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+    int iters = 0;
+    std::string err;
+
+    double* keep(int64_t count)
+    {
+        void* p = nullptr;
+        HIPCHK(hipMalloc(&p, (size_t)std::max<int64_t>(count, 1) * sizeof(double)));
+        owned.push_back(p);
+        return (double*)p;
+    }
+    // work on the worker streams starts after everything enqueued so far on
+    // the caller's stream ...
+    void fork()
+    {
+        HIPCHK(hipEventRecord(ev_fork, ust));
+        for (auto& x : w) HIPCHK(hipStreamWaitEvent(x.st, ev_fork, 0));
+    }
+    // ... and the caller's stream continues after the worker streams
+    void join()
+    {
+        for (int i = 0; i < 2; ++i) {
+            HIPCHK(hipEventRecord(ev_join[i], w[i].st));
+            HIPCHK(hipStreamWaitEvent(ust, ev_join[i], 0));
+        }
+    }
+    // worker b continues after what worker a has enqueued so far
+    void order(int a, int b)
+    {
+        HIPCHK(hipEventRecord(ev_join[a], w[a].st));
+        HIPCHK(hipStreamWaitEvent(w[b].st, ev_join[a], 0));
+    }
+    // f(w[0], net[0]) and f(w[1], net[1]) from two host threads
+    template <class F>
+    void both(F&& f)
+    {
+        std::exception_ptr e1;
+        std::thread t([&] {
+            try {
+                f(w[1], net[1]);
+            } catch (...) {
+                e1 = std::current_exception();
+            }
+        });
+        std::exception_ptr e0;
+        try {
+            f(w[0], net[0]);
+        } catch (...) {
+            e0 = std::current_exception();
+        }
+        t.join();
+        if (e0) std::rethrow_exception(e0);
+        if (e1) std::rethrow_exception(e1);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 static std::string g_init_err = "no error";
@@ -804,39 +992,50 @@ static void init_net(ctm_ctx* c, Net& N, int d)
     N.sv = c->keep(x);
 }
 
-static void reset_env(ctm_ctx* c, Net& N)
+static void reset_env(Worker& W, Net& N, int D)
 {
-    const int64_t D = c->D, d = N.d;
+    const int64_t d = N.d;
     N.xbk = N.xki = N.xib = 1;
-    ctmk::fill(c->st, N.C1, 1, 1.0);
-    ctmk::fill(c->st, N.C4, 1, 1.0);
-    ctmk::fill(c->st, N.Tk, D, 1.0 / std::sqrt((double)D));
-    ctmk::fill(c->st, N.Ti, d, 1.0 / std::sqrt((double)d));
-    ctmk::fill(c->st, N.Tb, D, 1.0 / std::sqrt((double)D));
-    ctmk::fill(c->st, N.s_old, 1, 1.0);
+    ctmk::fill(W.st, N.C1, 1, 1.0);
+    ctmk::fill(W.st, N.C4, 1, 1.0);
+    ctmk::fill(W.st, N.Tk, D, 1.0 / std::sqrt((double)D));
+    ctmk::fill(W.st, N.Ti, d, 1.0 / std::sqrt((double)d));
+    ctmk::fill(W.st, N.Tb, D, 1.0 / std::sqrt((double)D));
+    ctmk::fill(W.st, N.s_old, 1, 1.0);
     int one = 1;
-    HIPCHK(hipMemcpyAsync(N.n_old, &one, sizeof(int), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpyAsync(N.n_old, &one, sizeof(int), hipMemcpyHostToDevice, W.st));
+    HIPCHK(hipStreamSynchronize(W.st));
 }
 
+// A (host or device) -> D4-projected c->A and the two PEPOs; enqueued on
+// worker 0 (worker 1 is ordered after it).  The caller has made sure that no
+// earlier work still reads c->A.
 static void load_tensor(ctm_ctx* c, double beta, const double* A)
 {
+    Worker& W = c->w[0];
     const int64_t n = 2 * (int64_t)c->D * c->D * c->D * c->D;
-    double* raw = c->ws.alloc(n);
+    const Arena::Mark mk = W.ws.mark();
+    double* raw = W.ws.alloc(n);
     const bool dev = (c->cfg.flags & CTM_FLAG_DEVICE_PTRS) != 0;
-    HIPCHK(hipMemcpyAsync(raw, A, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
-    ctmk::d4_project(c->st, raw, c->A, c->D);
-    int* flag = (int*)c->ws.alloc(1);
-    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), c->st));
-    ctmk::finite_check(c->st, c->A, n, flag);
+    HIPCHK(hipMemcpyAsync(raw, A, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, W.st));
+    ctmk::d4_project(W.st, raw, c->A, c->D);
+    int* flag = (int*)W.ws.alloc(1);
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), W.st));
+    ctmk::finite_check(W.st, c->A, n, flag);
     int hflag = 0;
-    HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    ctmk::ising_pepo(c->st, c->net[0].O, beta);
-    ctmk::identity_pepo(c->st, c->net[1].O);
-    HIPCHK(hipStreamSynchronize(c->st));
-    c->ws.release({0, 0});
+    HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, W.st));
+    ctmk::ising_pepo(W.st, c->net[0].O, beta);
+    ctmk::identity_pepo(W.st, c->net[1].O);
+    HIPCHK(hipStreamSynchronize(W.st));
+    W.ws.release(mk);
+    c->order(0, 1);
     if (hflag) throw CtmError(CTM_ENUMERIC, "A contains NaN or Inf");
     c->beta = beta;
+}
+
+static void sync_workers(ctm_ctx* c)
+{
+    for (auto& x : c->w) HIPCHK(hipStreamSynchronize(x.st));
 }
 
 extern "C" {
@@ -876,27 +1075,28 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
     if (!c) { g_init_err = "host allocation failed"; return CTM_ENOMEM; }
     ctm_status s = guarded(c, [&] {
         c->cfg = *cfg;
-        c->profiling = (cfg->flags & CTM_FLAG_PROFILE) != 0;
-        if (const char* e = std::getenv("CTM_JACOBI_EXACT_MAX")) {   // testing aid
-            c->exact_min = std::atoll(e);
-            c->exact_area = c->exact_min * c->exact_min * 4;
-        }
         c->D = cfg->D;
         c->chi = cfg->chi;
         c->xmax = std::max(cfg->chi, 2 * 2 * cfg->D * cfg->D);
-        c->st = (hipStream_t)hip_stream;
+        c->ust = (hipStream_t)hip_stream;
         HIPCHK(hipGetDevice(&c->device));
         c->A = c->keep(2 * (int64_t)c->D * c->D * c->D * c->D);
-        c->part = c->keep(ctmk::kRedBlocks);
-        c->scal = c->keep(16);
-        c->icount = (int*)c->keep(1);
-        c->gws_cap = (int64_t)1 << 22;   // 32 MiB
-        c->gws = c->keep(c->gws_cap);
+        for (auto& x : c->w) {
+            x.setup(*cfg, c->D, c->A);
+            if (const char* e = std::getenv("CTM_JACOBI_EXACT_MAX")) {   // testing aid
+                x.exact_min = std::atoll(e);
+                x.exact_area = x.exact_min * x.exact_min * 4;
+            }
+        }
+        HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        for (auto& e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         init_net(c, c->net[0], 2);
         init_net(c, c->net[1], 1);
+        c->fork();
         load_tensor(c, beta, A);
-        reset_env(c, c->net[0]);
-        reset_env(c, c->net[1]);
+        reset_env(c->w[0], c->net[0], c->D);
+        reset_env(c->w[1], c->net[1], c->D);
+        c->join();
     });
     if (s != CTM_OK) {
         g_init_err = c->err;
@@ -916,25 +1116,28 @@ ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_del
     ctm_status s = guarded(c, [&] {
         const bool until = n_iter <= 0;
         const int budget = until ? std::max(0, c->cfg.max_iter - c->iters) : n_iter;
+        c->fork();
         for (int it = 0; it < budget; ++it) {
             // the first move from the product boundary never truncates
             const int64_t chi = (c->iters == 0) ? (int64_t)INT_MAX : (int64_t)c->chi;
-            c->step(c->net[0], chi, 0);
-            c->step(c->net[1], chi, 1);
-            HIPCHK(hipGetLastError());
+            c->both([&](Worker& W, Net& N) {
+                W.step(N, chi);
+                HIPCHK(hipGetLastError());
+            });
             ++c->iters;
             ++done;
             if (until || it == budget - 1) {
                 double h[2];
-                HIPCHK(hipMemcpyAsync(&h[0], c->net[0].delta, sizeof(double), hipMemcpyDeviceToHost, c->st));
-                HIPCHK(hipMemcpyAsync(&h[1], c->net[1].delta, sizeof(double), hipMemcpyDeviceToHost, c->st));
-                HIPCHK(hipStreamSynchronize(c->st));
+                for (int i = 0; i < 2; ++i)
+                    HIPCHK(hipMemcpyAsync(&h[i], c->net[i].delta, sizeof(double), hipMemcpyDeviceToHost, c->w[i].st));
+                sync_workers(c);
                 dl = std::max(h[0], h[1]);
                 if (!std::isfinite(dl)) throw CtmError(CTM_ENUMERIC, "non-finite spectrum");
                 if (until && c->iters > 1 && dl < c->cfg.tol) { conv = true; break; }
             }
         }
-        HIPCHK(hipStreamSynchronize(c->st));
+        c->join();
+        HIPCHK(hipStreamSynchronize(c->ust));
     });
     if (iters_done) *iters_done = done;
     if (last_delta) *last_delta = dl;
@@ -951,13 +1154,16 @@ ctm_status ctm_free_energy(ctm_ctx* c, double* f, double* lk3, double* lk2)
     if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
     double h[6] = {0, 0, 0, 0, 0, 0};
     ctm_status s = guarded(c, [&] {
-        c->values(c->net[0], nullptr, false);
-        c->values(c->net[1], nullptr, false);
-        ctmk::free_energy(c->st, c->net[0].sc + 4, c->net[1].sc + 4, c->beta, c->scal);
-        HIPCHK(hipMemcpyAsync(&h[0], c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipMemcpyAsync(&h[1], c->net[0].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipMemcpyAsync(&h[3], c->net[1].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
+        c->fork();
+        c->both([&](Worker& W, Net& N) { W.values(N, false); });
+        c->order(1, 0);
+        Worker& W = c->w[0];
+        ctmk::free_energy(W.st, c->net[0].sc + 4, c->net[1].sc + 4, c->beta, W.scal);
+        HIPCHK(hipMemcpyAsync(&h[0], W.scal, sizeof(double), hipMemcpyDeviceToHost, W.st));
+        HIPCHK(hipMemcpyAsync(&h[1], c->net[0].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
+        HIPCHK(hipMemcpyAsync(&h[3], c->net[1].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
+        HIPCHK(hipStreamSynchronize(W.st));
+        c->join();
         if (h[2] != 0.0 || h[4] != 0.0 || !std::isfinite(h[0]))
             throw CtmError(CTM_ENUMERIC, "non-positive or non-finite network value");
     });
@@ -974,19 +1180,22 @@ ctm_status ctm_grad(ctm_ctx* c, double* g)
     if (!c || !g) return CTM_EINVAL;
     if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
     return guarded(c, [&] {
-        c->values(c->net[0], nullptr, true);
-        c->values(c->net[1], nullptr, true);
+        c->fork();
+        c->both([&](Worker& W, Net& N) { W.values(N, true); });
+        c->order(1, 0);
+        Worker& W = c->w[0];
         const int n = 2 * c->D * c->D * c->D * c->D;
-        const Arena::Mark mk = c->ws.mark();
-        double* graw = c->ws.alloc(n);
-        double* gsym = c->ws.alloc(n);
-        ctmk::grad_combine(c->st, c->net[0].E, c->net[0].sc + 6, c->net[1].E, c->net[1].sc + 6,
+        const Arena::Mark mk = W.ws.mark();
+        double* graw = W.ws.alloc(n);
+        double* gsym = W.ws.alloc(n);
+        ctmk::grad_combine(W.st, c->net[0].E, c->net[0].sc + 6, c->net[1].E, c->net[1].sc + 6,
                            c->beta, graw, n);
-        ctmk::d4_project(c->st, graw, gsym, c->D);
+        ctmk::d4_project(W.st, graw, gsym, c->D);
         const bool dev = (c->cfg.flags & CTM_FLAG_DEVICE_PTRS) != 0;
-        HIPCHK(hipMemcpyAsync(g, gsym, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
-        c->ws.release(mk);
+        HIPCHK(hipMemcpyAsync(g, gsym, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, W.st));
+        HIPCHK(hipStreamSynchronize(W.st));
+        W.ws.release(mk);
+        c->join();
     });
 }
 
@@ -995,13 +1204,15 @@ ctm_status ctm_corner_spectrum(ctm_ctx* c, int which, double* s, int cap, int* n
     if (!c || !s || !n || (which != 2 && which != 3)) return CTM_EINVAL;
     if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
     return guarded(c, [&] {
-        Net& N = c->net[which == 3 ? 0 : 1];
+        const int i = which == 3 ? 0 : 1;
+        Net& N = c->net[i];
+        hipStream_t st = c->w[i].st;
         int cnt = 0;
-        HIPCHK(hipMemcpyAsync(&cnt, N.n_old, sizeof(int), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
+        HIPCHK(hipMemcpyAsync(&cnt, N.n_old, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         cnt = std::min(cnt, cap);
-        HIPCHK(hipMemcpyAsync(s, N.s_old, cnt * sizeof(double), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
+        HIPCHK(hipMemcpyAsync(s, N.s_old, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         *n = cnt;
     });
 }
@@ -1010,7 +1221,12 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A)
 {
     if (!c || !A) return CTM_EINVAL;
     if (!(beta > 0.0)) { c->err = "beta must be > 0"; return CTM_EINVAL; }
-    return guarded(c, [&] { load_tensor(c, beta, A); });
+    return guarded(c, [&] {
+        sync_workers(c);
+        c->fork();
+        load_tensor(c, beta, A);
+        c->join();
+    });
 }
 
 ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes)
@@ -1018,9 +1234,10 @@ ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes
     if (!c) return CTM_EINVAL;
     if (total_iters) *total_iters = c->iters;
     if (device_bytes) {
-        long long b = (long long)c->ws.bytes_held;
-        const int64_t x = c->xmax, D = c->D;
-        b += (long long)sizeof(double) * (2 * (2 * x * x + 2 * x * x * D + x * x * 2) + 2 * D * D * D * D);
+        long long b = 0;
+        for (const auto& x : c->w) b += (long long)x.ws.bytes_held + (long long)sizeof(double) * x.gws_cap;
+        const int64_t xm = c->xmax, D = c->D;
+        b += (long long)sizeof(double) * (2 * (2 * xm * xm + 2 * xm * xm * D + xm * xm * 2) + 2 * D * D * D * D);
         *device_bytes = b;
     }
     return CTM_OK;
@@ -1029,27 +1246,31 @@ ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes
 ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops)
 {
     if (!c || which < 0 || which > 2) return CTM_EINVAL;
-    if (!c->profiling) { c->err = "context not built with CTM_FLAG_PROFILE"; return CTM_ESTATE; }
+    if (!(c->cfg.flags & CTM_FLAG_PROFILE)) { c->err = "context not built with CTM_FLAG_PROFILE"; return CTM_ESTATE; }
     return guarded(c, [&] {
-        c->prof_collect();
-        if (launches) *launches = c->kstat[which].launches;
-        if (ms) *ms = c->kstat[which].ms;
-        if (flops) *flops = c->kstat[which].flops;
+        long long l = 0;
+        double t = 0.0, fl = 0.0;
+        for (auto& x : c->w) {
+            x.prof_collect();
+            l += x.kstat[which].launches;
+            t += x.kstat[which].ms;
+            fl += x.kstat[which].flops;
+        }
+        if (launches) *launches = l;
+        if (ms) *ms = t;
+        if (flops) *flops = fl;
     });
 }
 
 void ctm_destroy(ctm_ctx* c)
 {
     if (!c) return;
-    if (c->st || true) (void)hipStreamSynchronize(c->st);
-    c->ws.free_all();
+    for (auto& x : c->w) x.release();
+    if (c->ust) (void)hipStreamSynchronize(c->ust);
     for (void* p : c->owned) (void)hipFree(p);
-    for (auto& k : c->kstat)
-        for (auto& pr : k.pending) {
-            (void)hipEventDestroy(pr.first);
-            (void)hipEventDestroy(pr.second);
-        }
-    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (auto& e : c->ev_join)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
