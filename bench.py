@@ -29,6 +29,13 @@ from synth_inputs import WORKLOADS, workload_peps  # noqa: E402
 PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
 
+# kernel classes timed by the library's profile mode: name, roofline bound, peak
+KERNEL_CLASSES = {
+    0: ("gemm_f64_kernel (v_mfma_f64_16x16x4, split-K reduction included)", "mfma", PEAK_FP64_MFMA_TFLOPS),
+    1: ("jacobi_svd_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
+    2: ("cholqr_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
+}
+
 
 def gpu_eval(ctm, torch, w, A, g, stream, profile=False):
     c = ctm.SplitCTM(w["beta"], A, w["chi"], max_iter=w["max_iter"], tol=w["tol"],
@@ -114,23 +121,20 @@ def main():
     if not args.no_profile_pass:
         print("profile pass", file=sys.stderr, flush=True)
         c, pinfo = gpu_eval(ctm, torch, w, A, g, sp, profile=True)
-        stats = {k: c.kernel_stats(k) for k in (0, 1)}
+        stats = {k: c.kernel_stats(k) for k in KERNEL_CLASSES}
         c.close()
-        gl, gms, gfl = stats[0]
-        jl, jms, _ = stats[1]
-        if gms >= jms:
-            ach = gfl / (gms / 1e3) / 1e12
-            roofline = dict(kernel="gemm_f64_kernel (v_mfma_f64_16x16x4)", bound="mfma",
-                            achieved=ach, peak=PEAK_FP64_MFMA_TFLOPS, unit="TFLOP/s",
-                            frac=ach / PEAK_FP64_MFMA_TFLOPS, traffic=None,
-                            launches=gl, avg_launch_us=1e3 * gms / max(gl, 1),
-                            share_of_kernel_time=gms / (gms + jms))
-        else:
-            roofline = dict(kernel="jacobi_svd_kernel", bound="alu", achieved=None,
-                            peak=PEAK_FP64_VECTOR_TFLOPS, unit="TFLOP/s", frac=None,
-                            traffic=None, launches=jl, avg_launch_us=1e3 * jms / max(jl, 1),
-                            share_of_kernel_time=jms / (gms + jms),
-                            gemm_achieved_tflops=gfl / max(gms, 1e-9) / 1e9)
+        total_ms = sum(v[1] for v in stats.values())
+        dom = max(stats, key=lambda k: stats[k][1])
+        name, bound, peak = KERNEL_CLASSES[dom]
+        launches, kms, kfl = stats[dom]
+        ach = kfl / (kms / 1e3) / 1e12 if kms > 0 else None
+        roofline = dict(kernel=name, bound=bound, achieved=ach, peak=peak, unit="TFLOP/s",
+                        frac=(ach / peak) if ach is not None else None, traffic=None,
+                        launches=launches, avg_launch_us=1e3 * kms / max(launches, 1),
+                        share_of_kernel_time=kms / total_ms if total_ms > 0 else None,
+                        classes={KERNEL_CLASSES[k][0]: dict(launches=v[0], ms=v[1],
+                                                            tflops=(v[2] / (v[1] / 1e3) / 1e12) if v[1] > 0 else None)
+                                 for k, v in stats.items()})
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CTM_ABI_VERSION 1
+#define CTM_ABI_VERSION 2
 
 typedef struct ctm_ctx ctm_ctx;
 
@@ -61,10 +61,17 @@ typedef enum {
 
 typedef enum {
     CTM_FP64 = 0,       /* every contraction in float64                          */
-    CTM_FP32 = 1,       /* bulk contractions float32 in / float32 accumulate;    */
-                        /* projector factorisations, norms, f, g stay float64    */
-    CTM_BF16 = 2        /* bulk contractions bfloat16 in / float32 accumulate    */
+    CTM_FP32 = 1,       /* bulk contractions float32 products / float32 accumulate */
+    CTM_BF16 = 2        /* bulk contractions bfloat16 products / float32 accumulate */
 } ctm_precision;
+/* In the reduced-precision forms the bulk contractions of a move (absorption,
+ * projector environments rho_B rho_T, application of the projectors) run on
+ * the FP32 or BF16 matrix cores with FP32 accumulation; the projector
+ * factorisations, the corner spectrum, the normalisations and f and g stay
+ * FP64.  Tensors are stored in FP64 throughout (operands are rounded when
+ * they are staged for the matrix cores).  The reduced-precision phase ends
+ * when the spectrum change drops below max(tol, lp_tol); with refine = 1 the
+ * iteration then continues in FP64 until the change is below tol. */
 
 #define CTM_FLAG_DEVICE_PTRS 1
 #define CTM_FLAG_PROFILE 2      /* record HIP events around GEMM / Jacobi launches */
@@ -78,6 +85,9 @@ typedef struct {
     int flags;          /* CTM_FLAG_* bits                                        */
     int power_iters;    /* subspace iterations of the projector SVD (0: default)  */
     double svd_cutoff;  /* relative singular-value cutoff (0: default 1e-8)       */
+    double lp_tol;      /* end of the reduced-precision phase (0: 1e-6 FP32,      */
+                        /* 1e-3 BF16); ignored for CTM_FP64                       */
+    int refine;         /* 1: continue in FP64 to tol after that phase            */
 } ctm_config;
 
 /* Build a context: the PEPO O of the 3D Ising model at inverse temperature
@@ -121,10 +131,13 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A);
 ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes);
 
 /* Launch statistics of a context built with CTM_FLAG_PROFILE: which = 0 the
- * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernel, 2 the Cholesky QR kernel.  launches, summed kernel time
- * in ms (HIP events on the context stream around each launch) and algorithmic
- * flops (2 M N K per GEMM; 0 for the factorisations).  Synchronises the stream.  Any output
- * may be NULL.  CTM_ESTATE without CTM_FLAG_PROFILE. */
+ * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernel, 2 the Cholesky QR kernel,
+ * 3 the FP32 / BF16 MFMA GEMM kernel.
+ * launches, summed kernel time in ms (HIP events on the context's streams
+ * around each launch; the two network streams may overlap) and algorithmic
+ * flops: 2 M N K per GEMM (both GEMM classes); per Jacobi sweep and column pair 12 m (+ 6 n with V);
+ * 2 k^3 / 3 per Cholesky-QR factor.  Synchronises.  Any output may be NULL.
+ * CTM_ESTATE without CTM_FLAG_PROFILE. */
 ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops);
 
 /* Release a context.  NULL-safe. */

@@ -169,7 +169,7 @@ struct KStat {
 constexpr int kJacobiExact = 64;    // exact Jacobi SVD when min(m, n) <= this
 constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resident)
 constexpr int kOversample = 16;
-constexpr int64_t kCoreMax = 135;   // largest k x k factorisation held in LDS
+constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resident Jacobi)
 // relative pseudo-inverse cutoff of S^1/2: singular values of rho_B rho_T below
 // 1e-8 of the largest are dropped.  The subspace factorisation squares the
 // spectrum in its Gram steps, so 1e-8 is the smallest relative singular value
@@ -177,6 +177,11 @@ constexpr int64_t kCoreMax = 135;   // largest k x k factorisation held in LDS
 constexpr double kDefaultCutoff = 1e-8;
 constexpr int kJacobiSweeps = 40;
 constexpr int kMaxBatch = 16;       // projectors factorised together
+// spectrum-change floors of the reduced-precision phases (rounding noise of
+// the FP32 / BF16 products keeps the change of the normalised spectrum above
+// roughly these values)
+constexpr double kLpTolFp32 = 1e-6;
+constexpr double kLpTolBf16 = 1e-3;
 
 }  // namespace
 
@@ -199,9 +204,17 @@ struct Worker {
     int64_t gws_cap = 0;
     uint64_t svd_calls = 0;
     int64_t exact_min = kJacobiExact, exact_area = kJacobiExactArea;
+    int64_t trace_perm = 0;          // testing aid: log permutes of at least this many elements
+    int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
+    int cur = CTM_FP64;              // precision of the GEMMs issued now
     bool profiling = false;
-    KStat kstat[3];                  // [0] GEMM (MFMA), [1] Jacobi SVD, [2] Cholesky QR
+    KStat kstat[4];                  // [0] FP64 GEMM, [1] Jacobi SVD, [2] Cholesky QR, [3] FP32/BF16 GEMM
     std::vector<hipEvent_t> ev_pool;
+    // profile mode: sweeps of every Jacobi job, for its algorithmic flop count
+    static constexpr int kSweepSlots = 4096;
+    int* sweeps_dev = nullptr;
+    struct JobShape { int64_t m, n; bool v; };
+    std::vector<JobShape> sweep_jobs;
 
     void setup(const ctm_config& c, int d_bond, const double* a)
     {
@@ -215,6 +228,7 @@ struct Worker {
         icount = (int*)keep(kMaxBatch);
         gws_cap = (int64_t)1 << 22;   // 32 MiB
         gws = keep(gws_cap);
+        if (profiling) sweeps_dev = (int*)keep(kSweepSlots / 2);
     }
     void release()
     {
@@ -262,9 +276,25 @@ struct Worker {
         kstat[cls].flops += flops;
         kstat[cls].pending.push_back({a, b});
     }
+    // one-sided Jacobi, per sweep and column pair: three dot products (6m
+    // flops) and the rotation of the two columns of X (6m) and of V (6n)
+    void collect_sweeps()
+    {
+        if (sweep_jobs.empty()) return;
+        std::vector<int> sw(sweep_jobs.size());
+        HIPCHK(hipMemcpyAsync(sw.data(), sweeps_dev, sw.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < sw.size(); ++i) {
+            const JobShape& j = sweep_jobs[i];
+            kstat[1].flops += (double)sw[i] * 0.5 * (double)j.n * (double)(j.n - 1) *
+                              (12.0 * (double)j.m + (j.v ? 6.0 * (double)j.n : 0.0));
+        }
+        sweep_jobs.clear();
+    }
     void prof_collect()
     {
         HIPCHK(hipStreamSynchronize(st));
+        collect_sweeps();
         for (auto& k : kstat) {
             for (auto& pr : k.pending) {
                 float t = 0.f;
@@ -281,10 +311,22 @@ struct Worker {
               int64_t sC, int64_t nb)
     {
         hipEvent_t e = prof_begin();
-        ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, (int)nb,
-                       gws, gws_cap);
-        prof_end(0, e, 2.0 * (double)M * (double)N * (double)K * (double)nb);
+        if (cur == CTM_FP64)
+            ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, (int)nb,
+                           gws, gws_cap);
+        else
+            ctmk::gemm_lp(st, cur, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC,
+                          (int)nb, gws, gws_cap);
+        prof_end(cur == CTM_FP64 ? 0 : 3, e, 2.0 * (double)M * (double)N * (double)K * (double)nb);
     }
+
+    // GEMM precision for the lifetime of the guard
+    struct Prec {
+        Worker& w;
+        int old;
+        Prec(Worker& w_, int p) : w(w_), old(w_.cur) { w.cur = p; }
+        ~Prec() { w.cur = old; }
+    };
 
     // ---------------- allocation helpers
     double* keep(int64_t count)
@@ -340,6 +382,8 @@ struct Worker {
             pd.is[k] = istride[pos];
         }
         Tn out = tmp_dims(od, A.r);
+        if (trace_perm && out.n() >= trace_perm)
+            std::fprintf(stderr, "permute %s->%s %lld\n", li.c_str(), lo.c_str(), (long long)out.n());
         ctmk::permute(st, A.p, out.p, pd, out.n());
         return out;
     }
@@ -465,8 +509,14 @@ struct Worker {
                 r.U = tmp({r.n, r.m});
                 r.V = tmp({r.n, r.n});
                 r.S = tmp({r.n});
+                int* sw = nullptr;
+                if (profiling) {
+                    if ((int)sweep_jobs.size() == kSweepSlots) collect_sweeps();
+                    sw = sweeps_dev + sweep_jobs.size();
+                    sweep_jobs.push_back({r.m, r.n, r.want_v});
+                }
                 jb.job[jb.n++] = ctmk::JacobiJob{X.p, W.p, r.U.p, r.V.p, r.S.p, (int)r.m, (int)r.n,
-                                                 r.want_v ? 1 : 0, nullptr};
+                                                 r.want_v ? 1 : 0, sw};
             }
             hipEvent_t e = prof_begin();
             ctmk::jacobi_svd(st, jb, kJacobiSweeps);
@@ -483,8 +533,10 @@ struct Worker {
         for (size_t b0 = 0; b0 < Ys.size(); b0 += ctmk::kMaxJacobiBatch) {
             const size_t b1 = std::min(Ys.size(), b0 + (size_t)ctmk::kMaxJacobiBatch);
             ctmk::CholBatch cb{};
+            double fl = 0.0;
             for (size_t i = b0; i < b1; ++i) {
                 const int64_t k = Ys[i].d[0];
+                fl += 2.0 / 3.0 * (double)k * (double)k * (double)k;   // elimination: 2 sum_i i^2
                 Tn G = mm(Ys[i], false, Ys[i], true);
                 Ts[i] = tmp({k, k});
                 Tn work = tmp({2 * k});
@@ -492,7 +544,7 @@ struct Worker {
             }
             hipEvent_t e = prof_begin();
             ctmk::cholqr(st, cb, 1e-14);
-            prof_end(2, e, 0.0);
+            prof_end(2, e, fl);
         }
         for (size_t i = 0; i < Ys.size(); ++i) Ys[i] = mm(Ts[i], false, Ys[i], false);
     }
@@ -520,6 +572,7 @@ struct Worker {
     };
     void svd_batch(std::vector<SvdReq>& rq)
     {
+        Prec fp64(*this, CTM_FP64);   // factorisations stay FP64 in every precision form
         std::vector<JReq> ex;
         std::vector<size_t> ex_of, rnd;
         std::vector<bool> ex_t;
@@ -557,11 +610,11 @@ struct Worker {
         }
         if (rnd.empty()) return;
         // oversampling: near the cut the spectra of these environments are
-        // flat (sigma_{1.16 chi} / sigma_chi ~ 0.5), so the subspace extends
-        // to min(2 kk, 135) vectors (the largest core that stays in LDS) and
-        // six power steps resolve the kept directions to ~1e-10.  The bond
-        // gauge changes every iteration, so the previous subspace is no better
-        // a start than a random one.
+        // flat (sigma_{1.28 chi} / sigma_chi ~ 0.3-0.5), so the subspace extends
+        // to min(2 kk, 128) vectors (at least kk + 16) and ten power steps
+        // resolve the kept singular values to ~1e-11.  The bond gauge changes
+        // every iteration, so the previous subspace is no better a start than
+        // a random one.
         const size_t nr = rnd.size();
         std::vector<Tn> Pt(nr), Qt(nr);
         for (size_t j = 0; j < nr; ++j) {
@@ -572,13 +625,17 @@ struct Worker {
             Pt[j] = tmp({k, n});
             ctmk::randn(st, Pt[j].p, k * n, 0x5eedull + 7919ull * (++svd_calls));
         }
-        const int q = cfg.power_iters > 0 ? cfg.power_iters : 6;
-        orth(Pt);
+        // inside the power steps one Cholesky-QR pass keeps the basis well
+        // conditioned; the bases that enter the Rayleigh-Ritz core (last P, Q)
+        // get the second pass that makes them orthonormal
+        const int q = cfg.power_iters > 0 ? cfg.power_iters : 10;
+        cholqr_pass(Pt);
         for (int it = 0; it < q; ++it) {
             for (size_t j = 0; j < nr; ++j) Qt[j] = mm(Pt[j], false, rq[rnd[j]].M, true);   // (M P)^T
-            orth(Qt);
+            cholqr_pass(Qt);
             for (size_t j = 0; j < nr; ++j) Pt[j] = mm(Qt[j], false, rq[rnd[j]].M, false);  // (M^T Q)^T
-            orth(Pt);
+            if (it + 1 < q) cholqr_pass(Pt);
+            else orth(Pt);
         }
         for (size_t j = 0; j < nr; ++j) Qt[j] = mm(Pt[j], false, rq[rnd[j]].M, true);
         orth(Qt);
@@ -675,6 +732,7 @@ struct Worker {
 // --------------------------------------------------------------------------
 void Worker::step(Net& N, int64_t chi)
 {
+    Prec bulk_prec(*this, bulk);   // absorption, environments, projector application
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
     Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
@@ -810,7 +868,8 @@ void Worker::step(Net& N, int64_t chi)
     normalize(Ti_n);
     normalize(Tb_n);
 
-    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2
+    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form)
+    Prec spec64(*this, CTM_FP64);
     Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
     Tn R = ctr("ab,bc->ac", R1, R1);
     ctmk::trace(st, R.p, (int)k4, N.sc + 7);
@@ -834,6 +893,7 @@ void Worker::step(Net& N, int64_t chi)
 // with_env: also the bra environment into N.E and its overlap with A in N.sc[6]
 void Worker::values(Net& N, bool with_env)
 {
+    Prec fp64(*this, CTM_FP64);   // f and g are evaluated in FP64 in every form
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
     Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
@@ -900,7 +960,15 @@ struct ctm_ctx {
     Worker w[2];                     // one per network
     hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     int iters = 0;
+    bool lp_done = false;            // reduced-precision phase over (FP64 refinement runs)
     std::string err;
+
+    // spectrum change that ends the reduced-precision phase
+    double lp_tol() const
+    {
+        if (cfg.lp_tol > 0.0) return cfg.lp_tol;
+        return cfg.precision == CTM_FP32 ? kLpTolFp32 : kLpTolBf16;
+    }
 
     double* keep(int64_t count)
     {
@@ -1070,7 +1138,11 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
     if (cfg->D < 1 || cfg->D > 8) { g_init_err = "D must be in [1, 8]"; return CTM_EINVAL; }
     if (cfg->chi < 1 || cfg->chi > 512) { g_init_err = "chi must be in [1, 512]"; return CTM_EINVAL; }
     if (cfg->tol < 0.0 || cfg->max_iter < 0) { g_init_err = "tol and max_iter must be >= 0"; return CTM_EINVAL; }
-    if (cfg->precision != CTM_FP64) { g_init_err = "only CTM_FP64 is implemented"; return CTM_EINVAL; }
+    if (cfg->precision != CTM_FP64 && cfg->precision != CTM_FP32 && cfg->precision != CTM_BF16) {
+        g_init_err = "precision must be CTM_FP64, CTM_FP32 or CTM_BF16";
+        return CTM_EINVAL;
+    }
+    if (cfg->lp_tol < 0.0) { g_init_err = "lp_tol must be >= 0"; return CTM_EINVAL; }
     ctm_ctx* c = new (std::nothrow) ctm_ctx();
     if (!c) { g_init_err = "host allocation failed"; return CTM_ENOMEM; }
     ctm_status s = guarded(c, [&] {
@@ -1087,6 +1159,7 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
                 x.exact_min = std::atoll(e);
                 x.exact_area = x.exact_min * x.exact_min * 4;
             }
+            if (const char* e = std::getenv("CTM_TRACE_PERMUTE")) x.trace_perm = std::atoll(e);   // testing aid
         }
         HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         for (auto& e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1120,7 +1193,9 @@ ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_del
         for (int it = 0; it < budget; ++it) {
             // the first move from the product boundary never truncates
             const int64_t chi = (c->iters == 0) ? (int64_t)INT_MAX : (int64_t)c->chi;
+            const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;
             c->both([&](Worker& W, Net& N) {
+                W.bulk = prec;
                 W.step(N, chi);
                 HIPCHK(hipGetLastError());
             });
@@ -1133,7 +1208,15 @@ ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_del
                 sync_workers(c);
                 dl = std::max(h[0], h[1]);
                 if (!std::isfinite(dl)) throw CtmError(CTM_ENUMERIC, "non-finite spectrum");
-                if (until && c->iters > 1 && dl < c->cfg.tol) { conv = true; break; }
+                if (until && c->iters > 1) {
+                    if (prec == CTM_FP64) {
+                        if (dl < c->cfg.tol) { conv = true; break; }
+                    } else if (dl < std::max(c->cfg.tol, c->lp_tol())) {
+                        // end of the reduced-precision phase: stop, or refine in FP64
+                        if (!c->cfg.refine) { conv = true; break; }
+                        c->lp_done = true;
+                    }
+                }
             }
         }
         c->join();
@@ -1226,6 +1309,7 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A)
         c->fork();
         load_tensor(c, beta, A);
         c->join();
+        c->lp_done = false;
     });
 }
 
@@ -1245,7 +1329,7 @@ ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes
 
 ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops)
 {
-    if (!c || which < 0 || which > 2) return CTM_EINVAL;
+    if (!c || which < 0 || which > 3) return CTM_EINVAL;
     if (!(c->cfg.flags & CTM_FLAG_PROFILE)) { c->err = "context not built with CTM_FLAG_PROFILE"; return CTM_ESTATE; }
     return guarded(c, [&] {
         long long l = 0;

@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -181,6 +182,179 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
         hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
     else
         hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
+    if (ksplit > 1) {
+        const int64_t total = (int64_t)batch * M * N;
+        const int g = (int)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(gemm_reduce_kernel, dim3(g), dim3(256), 0, s, P, M, N, ksplit, C, ldc, sC, total);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM with FP32 or BF16 products and FP32 accumulation (reduced-precision
+// forms of the bulk contractions).  Operands and result stay FP64 in memory:
+// the operands are rounded (to nearest even) when staged into LDS, the
+// matrix cores multiply in the reduced precision and accumulate in FP32, and
+// alpha * acc is written back as FP64.  Tiles as in gemm_f64_kernel; the LDS
+// tiles keep k contiguous ([row][k]) so that a lane's k-run is one load.
+//   FP32: v_mfma_f32_16x16x4_f32   a = A[l%16][l/16], b = B[l/16][l%16]
+//   BF16: v_mfma_f32_16x16x32_bf16 a = A[l%16][8(l/16) .. +7], b likewise
+//   result: acc[r] = C[4(l/16) + r][l%16]
+// ---------------------------------------------------------------------------
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int LK = 32;             // K step held in LDS
+constexpr int LGL = (GT * LK) / 256;
+
+__device__ inline unsigned short to_bf16_bits(double x)
+{
+    const float f = (float)x;
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
+    return (unsigned short)(u >> 16);
+}
+
+template <bool TA, bool TB, int P>   // P = 1: FP32, P = 2: BF16
+__global__ __launch_bounds__(256) void gemm_lp_kernel(
+    int M, int N, int K, double alpha,
+    const double* __restrict__ A, int64_t lda, int64_t sA,
+    const double* __restrict__ B, int64_t ldb, int64_t sB,
+    double beta, double* __restrict__ C, int64_t ldc, int64_t sC,
+    int ksplit, int kchunk, double* __restrict__ Pp)
+{
+    typedef typename std::conditional<P == 1, float, unsigned short>::type elem;
+    constexpr int PAD = (P == 1) ? 1 : 8;        // keeps 16-byte alignment of bf16 k-runs
+    __shared__ __attribute__((aligned(16))) elem As[GT][LK + PAD];
+    __shared__ __attribute__((aligned(16))) elem Bs[GT][LK + PAD];
+    const int z = blockIdx.z;
+    const int bz = z / ksplit, sp = z % ksplit;
+    A += bz * sA;
+    B += bz * sB;
+    const int kbeg = sp * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    flt4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    double ra[LGL], rb[LGL];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < LGL; ++t) {
+            const int e = tid + t * 256;
+            int mm, kk;
+            if (!TA) { kk = e % LK; mm = e / LK; } else { mm = e % GT; kk = e / GT; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            ra[t] = (gm < M && gk < kend) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < LGL; ++t) {
+            const int e = tid + t * 256;
+            int nn, kk;
+            if (!TB) { nn = e % GT; kk = e / GT; } else { kk = e % LK; nn = e / LK; }
+            const int gn = n0 + nn, gk = k0 + kk;
+            rb[t] = (gn < N && gk < kend) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.0;
+        }
+    };
+    auto cvt = [](double x) -> elem {
+        if constexpr (P == 1) return (float)x;
+        else return to_bf16_bits(x);
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int t = 0; t < LGL; ++t) {
+            const int e = tid + t * 256;
+            int mm, kk;
+            if (!TA) { kk = e % LK; mm = e / LK; } else { mm = e % GT; kk = e / GT; }
+            As[mm][kk] = cvt(ra[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < LGL; ++t) {
+            const int e = tid + t * 256;
+            int nn, kk;
+            if (!TB) { nn = e % GT; kk = e / GT; } else { kk = e % LK; nn = e / LK; }
+            Bs[nn][kk] = cvt(rb[t]);
+        }
+    };
+
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += LK) {
+        stage();
+        __syncthreads();
+        if (k0 + LK < kend) fetch(k0 + LK);
+        const int r16 = lane & 15, q = lane >> 4;
+        if constexpr (P == 1) {
+#pragma unroll
+            for (int kk = 0; kk < LK; kk += 4) {
+                const float a0 = As[wm * 32 + r16][kk + q], a1 = As[wm * 32 + 16 + r16][kk + q];
+                const float b0 = Bs[wn * 32 + r16][kk + q], b1 = Bs[wn * 32 + 16 + r16][kk + q];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        } else {
+            const bf16x8 a0 = *(const bf16x8*)&As[wm * 32 + r16][8 * q];
+            const bf16x8 a1 = *(const bf16x8*)&As[wm * 32 + 16 + r16][8 * q];
+            const bf16x8 b0 = *(const bf16x8*)&Bs[wn * 32 + r16][8 * q];
+            const bf16x8 b1 = *(const bf16x8*)&Bs[wn * 32 + 16 + r16][8 * q];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double* out;
+    int64_t ldo;
+    if (ksplit > 1) { out = Pp + (int64_t)z * M * N; ldo = N; }
+    else { out = C + bz * sC; ldo = ldc; }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (gm < M && gn < N) {
+                    double* c = out + (int64_t)gm * ldo + gn;
+                    const double v = alpha * (double)acc[i][j][r];
+                    *c = (beta == 0.0 || ksplit > 1) ? v : v + beta * (*c);
+                }
+            }
+}
+
+void gemm_lp(hipStream_t s, int prec, bool ta, bool tb, int M, int N, int K, double alpha,
+             const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
+             double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap)
+{
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    int ksplit = (beta == 0.0 && ws) ? gemm_split_plan(M, N, K, batch, ws_cap) : 1;
+    int kchunk = K;
+    if (ksplit > 1) {
+        kchunk = (((K + ksplit - 1) / ksplit) + LK - 1) / LK * LK;
+        ksplit = (K + kchunk - 1) / kchunk;
+    }
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, batch * ksplit);
+    dim3 block(256);
+    double* P = ksplit > 1 ? ws : nullptr;
+#define CTM_LP_LAUNCH(TA_, TB_, P_) \
+    hipLaunchKernelGGL((gemm_lp_kernel<TA_, TB_, P_>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P)
+    if (prec == 1) {
+        if (!ta && !tb) CTM_LP_LAUNCH(false, false, 1);
+        else if (ta && !tb) CTM_LP_LAUNCH(true, false, 1);
+        else if (!ta && tb) CTM_LP_LAUNCH(false, true, 1);
+        else CTM_LP_LAUNCH(true, true, 1);
+    } else {
+        if (!ta && !tb) CTM_LP_LAUNCH(false, false, 2);
+        else if (ta && !tb) CTM_LP_LAUNCH(true, false, 2);
+        else if (!ta && tb) CTM_LP_LAUNCH(false, true, 2);
+        else CTM_LP_LAUNCH(true, true, 2);
+    }
+#undef CTM_LP_LAUNCH
     if (ksplit > 1) {
         const int64_t total = (int64_t)batch * M * N;
         const int g = (int)std::min<int64_t>((total + 255) / 256, 4096);
@@ -774,20 +948,185 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
     }
 }
 
+// Small problems (m, n <= 128, X in LDS): every column pair of a round is
+// served by 16 lanes; lanes 0-7 hold 16 rows each of the two columns of X,
+// lanes 8-15 16 rows each of the two columns of V.  All loads of a round are
+// issued together and V's (global) loads overlap the dot products and their
+// reduction; the rotation is applied from registers.
+typedef __attribute__((address_space(1))) double gdouble;
+constexpr int kSmallJacobi = 128;
+
+template <bool WL>
+__global__ __launch_bounds__(1024) void jacobi_small_kernel(JacobiBatch jobs, int max_sweeps)
+{
+    extern __shared__ double lds[];
+    const JacobiJob jb = jobs.job[blockIdx.x];
+    const int m = jb.m, n = jb.n;
+    const bool acc_v = jb.want_v != 0;
+    double* X = lds;
+    double* Wl = lds + (int64_t)m * n;              // WL: V in LDS
+    gdouble* Wg = (gdouble*)jb.W;                    // !WL: V in global memory
+    const int ne = n + (n & 1);
+    const int npairs = ne / 2;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int grp = tid >> 4, l16 = tid & 15, half = l16 >> 3, sub = l16 & 7;
+    __shared__ int rotated;
+    __shared__ double sig[kSmallJacobi];
+    __shared__ int rnk[kSmallJacobi];
+    __shared__ double fro2;
+
+    for (int i = tid; i < m * n; i += nthr) X[i] = jb.X[i];
+    if (acc_v) {
+        for (int i = tid; i < n * n; i += nthr) {
+            const double v = ((i / n) == (i % n)) ? 1.0 : 0.0;
+            if (WL) Wl[i] = v;
+            else Wg[i] = v;
+        }
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += nthr) {
+        double v = 0.0;
+        for (int r = 0; r < m; ++r) v += X[j * m + r] * X[j * m + r];
+        sig[j] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int j = 0; j < n; ++j) t += sig[j];
+        fro2 = t;
+    }
+    __syncthreads();
+    const double noise2 = 1e-30 * fro2;
+    const double tol = 2.0 * sqrt((double)m) * 2.220446049250313e-16;
+
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int step = 0; step < ne - 1; ++step) {
+            int p = 0, q = 0;
+            bool active = grp < npairs;
+            if (active) {
+                if (grp == 0) { p = ne - 1; q = step; }
+                else { p = (step + grp) % (ne - 1); q = (step - grp + (ne - 1)) % (ne - 1); }
+                if (p >= n || q >= n) active = false;
+                if (p > q) { const int t = p; p = q; q = t; }
+            }
+            double a[16], b[16];
+            double al = 0.0, be = 0.0, ga = 0.0;
+            if (active && half == 1 && acc_v) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int r = sub + 8 * u;
+                    a[u] = r < n ? (WL ? Wl[p * n + r] : Wg[p * n + r]) : 0.0;
+                    b[u] = r < n ? (WL ? Wl[q * n + r] : Wg[q * n + r]) : 0.0;
+                }
+            }
+            if (active && half == 0) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int r = sub + 8 * u;
+                    a[u] = r < m ? X[p * m + r] : 0.0;
+                    b[u] = r < m ? X[q * m + r] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    al += a[u] * a[u];
+                    be += b[u] * b[u];
+                    ga += a[u] * b[u];
+                }
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) {
+                al += __shfl_xor(al, o, 16);
+                be += __shfl_xor(be, o, 16);
+                ga += __shfl_xor(ga, o, 16);
+            }
+            if (active && ga != 0.0 && al > noise2 && be > noise2 && fabs(ga) > tol * sqrt(al * be)) {
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                if (half == 0) {
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int r = sub + 8 * u;
+                        if (r < m) {
+                            X[p * m + r] = c * a[u] - sn * b[u];
+                            X[q * m + r] = sn * a[u] + c * b[u];
+                        }
+                    }
+                    if (l16 == 0) rotated = 1;
+                } else if (acc_v) {
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int r = sub + 8 * u;
+                        if (r < n) {
+                            const double va = c * a[u] - sn * b[u], vb = sn * a[u] + c * b[u];
+                            if (WL) { Wl[p * n + r] = va; Wl[q * n + r] = vb; }
+                            else { Wg[p * n + r] = va; Wg[q * n + r] = vb; }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (rotated == 0) {
+            if (jb.sweeps && tid == 0) jb.sweeps[0] = sweep + 1;
+            break;
+        }
+        __syncthreads();
+        if (sweep + 1 == max_sweeps && jb.sweeps && tid == 0) jb.sweeps[0] = max_sweeps;
+    }
+    // singular values = column norms; outputs sorted by descending value
+    for (int j = tid; j < n; j += nthr) {
+        double v = 0.0;
+        for (int r = 0; r < m; ++r) v += X[j * m + r] * X[j * m + r];
+        sig[j] = sqrt(v);
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += nthr) {
+        int r = 0;
+        const double sj = sig[j];
+        for (int i = 0; i < n; ++i) {
+            const double si = sig[i];
+            r += (si > sj) || (si == sj && i < j);
+        }
+        rnk[j] = r;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * m; e += nthr) {
+        const int j = e / m, r = e % m;
+        const double sj = sig[j];
+        jb.U[(int64_t)rnk[j] * m + r] = X[e] * (sj > 0.0 ? 1.0 / sj : 0.0);
+    }
+    if (acc_v) {
+        for (int e = tid; e < n * n; e += nthr) {
+            const int j = e / n, r = e % n;
+            jb.V[(int64_t)rnk[j] * n + r] = WL ? Wl[e] : Wg[e];
+        }
+    }
+    for (int j = tid; j < n; j += nthr) jb.S[rnk[j]] = sig[j];
+}
+
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
 {
     if (jobs.n <= 0) return;
-    bool xl = true, wl = true;
+    bool xl = true, wl = true, small = true;
     int64_t need_x = 0, need_w = 0;
     for (int i = 0; i < jobs.n; ++i) {
-        const int64_t mn = (int64_t)jobs.job[i].m * jobs.job[i].n;
-        const int64_t nn = jobs.job[i].want_v ? (int64_t)jobs.job[i].n * jobs.job[i].n : 0;
+        const JacobiJob& j = jobs.job[i];
+        const int64_t mn = (int64_t)j.m * j.n;
+        const int64_t nn = j.want_v ? (int64_t)j.n * j.n : 0;
         xl = xl && mn <= kJacobiLdsDoubles;
         wl = wl && mn + nn <= kJacobiLdsDoubles;
+        small = small && j.m <= kSmallJacobi && j.n <= kSmallJacobi;
         need_x = std::max(need_x, mn);
         need_w = std::max(need_w, mn + nn);
     }
-    if (xl && wl)
+    if (small && wl)
+        hipLaunchKernelGGL((jacobi_small_kernel<true>), dim3(jobs.n), dim3(1024), need_w * sizeof(double), s, jobs, max_sweeps);
+    else if (small)
+        hipLaunchKernelGGL((jacobi_small_kernel<false>), dim3(jobs.n), dim3(1024), need_x * sizeof(double), s, jobs, max_sweeps);
+    else if (xl && wl)
         hipLaunchKernelGGL((jacobi_svd_kernel<true, true>), dim3(jobs.n), dim3(1024), need_w * sizeof(double), s, jobs, max_sweeps);
     else if (xl)
         hipLaunchKernelGGL((jacobi_svd_kernel<true, false>), dim3(jobs.n), dim3(1024), need_x * sizeof(double), s, jobs, max_sweeps);
@@ -863,17 +1202,112 @@ __global__ __launch_bounds__(1024) void cholqr_kernel(CholBatch jobs, double shi
     }
 }
 
+// k <= 128: the same elimination with the matrix held in registers.  Row i
+// lives in wave i % 16 (slot i / 16), each lane holding the entries e = lane
+// and lane + 64 of that row of the Schur complement S and of the elimination
+// matrix X.  Step j: the owner of row j publishes S_j and X_j through LDS
+// (double-buffered, one barrier per step), and every row i > j applies
+// S_i -= f S_j, X_i -= f X_j with f = S_ji / S_jj (full rows keep S symmetric
+// up to rounding, so S_ji stands for S_ij).  LDS traffic per step is one row
+// pair, not the whole matrix.
+constexpr int kCholReg = 128;
+
+__global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double shift)
+{
+    __shared__ double dsc[kCholReg];
+    __shared__ double rowS[2][kCholReg];
+    __shared__ double rowX[2][kCholReg];
+    const CholJob jb = jobs.job[blockIdx.x];
+    const int k = jb.k;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = 16, SLOTS = kCholReg / NW;
+    for (int i = tid; i < k; i += blockDim.x) {
+        const double v = jb.G[(int64_t)i * k + i];
+        dsc[i] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    }
+    __syncthreads();
+    double S[SLOTS][2], Xr[SLOTS][2];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int i = wave + NW * s;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = lane + 64 * u;
+            const bool ok = i < k && e < k;
+            S[s][u] = ok ? jb.G[(int64_t)i * k + e] * dsc[i] * dsc[e] + (i == e ? shift : 0.0) : 0.0;
+            Xr[s][u] = (ok && i == e) ? 1.0 : 0.0;
+        }
+    }
+    for (int j = 0; j < k; ++j) {
+        const int buf = j & 1;
+        if (wave == j % NW) {
+            const int sj = j / NW;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s)
+                if (s == sj) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int e = lane + 64 * u;
+                        if (e < k) {
+                            rowS[buf][e] = S[s][u];
+                            rowX[buf][e] = Xr[s][u];
+                        }
+                    }
+                }
+        }
+        __syncthreads();
+        const double pj = rowS[buf][j];
+        const double inv = pj > 0.0 ? 1.0 / pj : 0.0;
+        double sj[2], xj[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = lane + 64 * u;
+            sj[u] = e < k ? rowS[buf][e] : 0.0;
+            xj[u] = e < k ? rowX[buf][e] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int i = wave + NW * s;
+            if (i > j && i < k) {
+                const double f = rowS[buf][i] * inv;   // S_ij = S_ji (S symmetric)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    S[s][u] -= f * sj[u];
+                    Xr[s][u] -= f * xj[u];
+                }
+            }
+        }
+    }
+    // pivots p_i = S_ii; T[i][c] = p_i^-1/2 X_ic d_c
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int i = wave + NW * s;
+        const double pii = __shfl((i >> 6) ? S[s][1] : S[s][0], i & 63, 64);
+        const double di = pii > 0.0 ? 1.0 / sqrt(pii) : 0.0;
+        if (i < k) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int c = lane + 64 * u;
+                if (c < k) jb.T[(int64_t)i * k + c] = c <= i ? di * Xr[s][u] * dsc[c] : 0.0;
+            }
+        }
+    }
+}
+
 void cholqr(hipStream_t s, const CholBatch& jobs, double shift)
 {
     if (jobs.n <= 0) return;
     int64_t need = 0;
-    bool fits = true;
+    bool fits = true, reg = true;
     for (int i = 0; i < jobs.n; ++i) {
         const int64_t kk = jobs.job[i].k;
         fits = fits && kk * kk + 2 * kk <= kCholLdsDoubles;
+        reg = reg && kk <= kCholReg;
         need = std::max(need, kk * kk + 2 * kk);
     }
-    if (fits)
+    if (reg)
+        hipLaunchKernelGGL(cholqr_reg_kernel, dim3(jobs.n), dim3(1024), 0, s, jobs, shift);
+    else if (fits)
         hipLaunchKernelGGL((cholqr_kernel<true>), dim3(jobs.n), dim3(1024), need * sizeof(double), s, jobs, shift);
     else
         hipLaunchKernelGGL((cholqr_kernel<false>), dim3(jobs.n), dim3(1024), 0, s, jobs, shift);

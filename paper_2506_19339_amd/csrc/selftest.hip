@@ -38,6 +38,25 @@ int ctm_selftest_gemm(int ta, int tb, int M, int N, int K, int batch, const doub
     return rc;
 }
 
+// the same with FP32 (prec 1) or BF16 (prec 2) products and FP32 accumulation
+int ctm_selftest_gemm_lp(int prec, int ta, int tb, int M, int N, int K, int batch, const double* A,
+                         const double* B, double* C, long long ws_cap)
+{
+    const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
+    double *dA = dev_copy(A, na), *dB = dev_copy(B, nb), *dC = dev_copy<double>(nullptr, nc);
+    double* dW = ws_cap > 0 ? dev_copy<double>(nullptr, (size_t)ws_cap) : nullptr;
+    if (!dA || !dB || !dC || (ws_cap > 0 && !dW)) return 1;
+    ctmk::gemm_lp(nullptr, prec, ta != 0, tb != 0, M, N, K, 1.0, dA, ta ? M : K, (int64_t)M * K, dB,
+                  tb ? K : N, (int64_t)K * N, 0.0, dC, N, (int64_t)M * N, batch, dW, ws_cap);
+    int rc = hipMemcpy(C, dC, nc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
+    rc |= hipDeviceSynchronize() != hipSuccess;
+    (void)hipFree(dA);
+    (void)hipFree(dB);
+    (void)hipFree(dC);
+    if (dW) (void)hipFree(dW);
+    return rc;
+}
+
 // number of K slices gemm_f64 uses for this shape and workspace
 int ctm_selftest_gemm_splits(int M, int N, int K, int batch, long long ws_cap)
 {

@@ -31,7 +31,8 @@ class CtmError(RuntimeError):
 class _Config(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int), ("chi", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
-                ("power_iters", ctypes.c_int), ("svd_cutoff", ctypes.c_double)]
+                ("power_iters", ctypes.c_int), ("svd_cutoff", ctypes.c_double),
+                ("lp_tol", ctypes.c_double), ("refine", ctypes.c_int)]
 
 
 _LIB = None
@@ -94,7 +95,8 @@ class SplitCTM:
     """
 
     def __init__(self, beta, A, chi, max_iter=100, tol=0.0, precision=CTM_FP64,
-                 power_iters=0, svd_cutoff=0.0, stream=None, lib=None, profile=False):
+                 power_iters=0, svd_cutoff=0.0, stream=None, lib=None, profile=False,
+                 lp_tol=0.0, refine=False):
         self._lib = lib or load_library()
         self._ctx = ctypes.c_void_p()
         D = int(np.shape(A)[1])
@@ -102,7 +104,7 @@ class SplitCTM:
         if profile:
             flags |= CTM_FLAG_PROFILE
         cfg = _Config(D, int(chi), int(max_iter), float(tol), int(precision), flags,
-                      int(power_iters), float(svd_cutoff))
+                      int(power_iters), float(svd_cutoff), float(lp_tol), int(bool(refine)))
         st = self._lib.ctm_init(ctypes.byref(cfg), float(beta), ptr,
                                 ctypes.c_void_p(stream or 0), ctypes.byref(self._ctx))
         del keep

@@ -20,6 +20,7 @@ def lib():
     L = ctypes.CDLL(SELFTEST)
     dp = ctypes.POINTER(ctypes.c_double)
     L.ctm_selftest_gemm.argtypes = [ctypes.c_int] * 6 + [dp, dp, dp, ctypes.c_longlong]
+    L.ctm_selftest_gemm_lp.argtypes = [ctypes.c_int] * 7 + [dp, dp, dp, ctypes.c_longlong]
     L.ctm_selftest_gemm_splits.argtypes = [ctypes.c_int] * 4 + [ctypes.c_longlong]
     L.ctm_selftest_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
     L.ctm_selftest_cholqr.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
@@ -57,10 +58,43 @@ def test_gemm_split_k_matches_numpy(lib, ta, tb, M, N, K, batch):
     _gemm_case(lib, ta, tb, M, N, K, batch, cap)
 
 
-@pytest.mark.parametrize("k,rank", [(1, 1), (16, 16), (100, 100), (135, 135), (135, 90), (141, 141), (160, 160)])
+def _round_bf16(x):
+    """float64 -> float32 (nearest even) -> bfloat16 (nearest even), as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("M,N,K,batch,cap", [(16, 16, 32, 1, 0), (65, 130, 17, 1, 0), (200, 37, 300, 3, 0),
+                                             (135, 1000, 1000, 1, 1 << 22), (1000, 100, 1000, 1, 0)])
+def test_gemm_reduced_precision(lib, prec, ta, tb, M, N, K, batch, cap):
+    """FP32 / BF16 products with FP32 accumulation: equal to the exact product
+    of the rounded operands up to FP32 accumulation error."""
+    rng = np.random.default_rng(M + 3 * N + 7 * K + prec)
+    A = rng.standard_normal((batch, K, M) if ta else (batch, M, K))
+    B = rng.standard_normal((batch, N, K) if tb else (batch, K, N))
+    C = np.zeros((batch, M, N))
+    assert lib.ctm_selftest_gemm_lp(prec, ta, tb, M, N, K, batch, _p(A), _p(B), _p(C), cap) == 0
+    rnd = (lambda x: np.asarray(x, np.float32).astype(np.float64)) if prec == 1 else _round_bf16
+    Ar, Br = rnd(A), rnd(B)
+    ref = np.matmul(Ar.transpose(0, 2, 1) if ta else Ar, Br.transpose(0, 2, 1) if tb else Br)
+    mag = np.matmul(np.abs(Ar.transpose(0, 2, 1) if ta else Ar), np.abs(Br.transpose(0, 2, 1) if tb else Br))
+    # FP32 accumulation of K products: |error| <= ~K u32 sum|a||b|, u32 = 2^-24
+    assert np.all(np.abs(C - ref) <= 2.0 * K * 2.0 ** -24 * mag + 1e-300)
+    # and the rounding of the operands is what separates C from the FP64 product
+    exact = np.matmul(A.transpose(0, 2, 1) if ta else A, B.transpose(0, 2, 1) if tb else B)
+    u = 2.0 ** -24 if prec == 1 else 2.0 ** -8
+    assert np.max(np.abs(C - exact) / (np.abs(exact).max() + 1e-300)) <= 4 * u * np.sqrt(K) + 1e-6 * (prec == 1)
+
+
+@pytest.mark.parametrize("k,rank", [(1, 1), (16, 16), (100, 100), (128, 128), (128, 90), (135, 135), (135, 90),
+                                    (141, 141), (160, 160)])
 def test_cholqr_factor(lib, k, rank):
-    """T = L^-1 D with L L^T = D G D + shift I, T lower triangular (k = 160
-    takes the global-memory path).  Full rank: T matches LAPACK's factor.
+    """T = L^-1 D with L L^T = D G D + shift I, T lower triangular (k <= 128:
+    register-resident kernel; 135, 141: LDS; 160: global memory).  Full rank: T matches LAPACK's factor.
     Rank deficient: the factor is as ill-conditioned as 1/shift, so what is
     checked is the property the subspace iteration needs, that two passes
     give orthonormal rows."""
@@ -94,7 +128,8 @@ def test_cholqr_factor(lib, k, rank):
         assert np.max(np.abs(Q2 @ Q2.T - np.eye(k))) <= 1e-9
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (8, 8), (33, 17), (64, 64), (100, 100), (300, 120), (256, 256)])
+@pytest.mark.parametrize("m,n", [(1, 1), (8, 8), (33, 17), (64, 64), (100, 100), (128, 128), (128, 117),
+                                 (129, 128), (300, 120), (256, 256)])
 def test_jacobi_svd_matches_numpy(lib, m, n):
     rng = np.random.default_rng(m + 100 * n)
     X = rng.standard_normal((m, n))
