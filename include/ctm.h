@@ -69,9 +69,12 @@ typedef enum {
  * the FP32 or BF16 matrix cores with FP32 accumulation; the projector
  * factorisations, the corner spectrum, the normalisations and f and g stay
  * FP64.  Tensors are stored in FP64 throughout (operands are rounded when
- * they are staged for the matrix cores).  The reduced-precision phase ends
- * when the spectrum change drops below max(tol, lp_tol); with refine = 1 the
- * iteration then continues in FP64 until the change is below tol. */
+ * they are staged for the matrix cores).  During the reduced-precision phase
+ * the relative pseudo-inverse cutoff is raised to the rounding level of the
+ * products (1e-7 FP32, 1e-2 BF16).  The phase ends when the spectrum change
+ * drops below max(tol, lp_tol); with refine = 1 the iteration then continues
+ * in FP64 (with svd_cutoff) until the change is below tol, and the phase also
+ * ends once half of max_iter is spent. */
 
 #define CTM_FLAG_DEVICE_PTRS 1
 #define CTM_FLAG_PROFILE 2      /* record HIP events around GEMM / Jacobi launches */
@@ -98,13 +101,28 @@ typedef struct {
 ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A,
                     void* hip_stream, ctm_ctx** out);
 
-/* Run n_iter split-CTMRG iterations on both networks (n_iter <= 0: iterate
- * until the spectrum change of both networks is below cfg->tol or max_iter
- * iterations have been done in total; then CTM_ENOCONV if tol was not met).
- * iters_done (may be NULL) receives the iterations done by this call and
- * last_delta (may be NULL) the larger of the two spectrum changes of the last
- * iteration. */
+/* Run split-CTMRG iterations on both networks.  n_iter > 0: exactly n_iter
+ * moves.  n_iter == 0: until the spectrum change of both networks is below
+ * cfg->tol, or max_iter moves since init or the last ctm_reset_tensor (then
+ * CTM_ENOCONV).  n_iter < 0: the same stopping rule for at most -n_iter moves
+ * (a slice; CTM_ENOCONV only when max_iter is reached).  iters_done (may be
+ * NULL) receives the moves done by this call and last_delta (may be NULL) the
+ * larger of the two spectrum changes of the last move. */
 ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_delta);
+
+/* Continuous-batching form of ctm_iterate for n (1..64) distinct contexts
+ * (serving: independent f-and-gradient requests, any shapes).  In every move
+ * the two networks of every still-active context step concurrently, each on
+ * its own stream and host thread; each context applies the stopping rule of
+ * ctm_iterate for the given n_iter and leaves the batch when it is done, so a
+ * scheduler can call it with n_iter < 0 in slices and add or retire contexts
+ * between calls.  The results of a context do not depend on the other members
+ * of the batch.  iters_done, last_delta, converged (1 when the stopping rule
+ * was met) and status (each may be NULL) receive one entry per context; the
+ * return value is the first non-OK status (CTM_EINVAL for a NULL or repeated
+ * context or n out of range). */
+ctm_status ctm_iterate_batch(ctm_ctx** cs, int n, int n_iter, int* iters_done, double* last_delta,
+                             int* converged, int* status);
 
 /* f = -(ln kappa3 - ln kappa2) / beta with the per-site values kappa of the
  * triple- and double-layer networks estimated as n1 n0 / (n2h n2v) from the
@@ -124,7 +142,9 @@ ctm_status ctm_grad(ctm_ctx* c, double* g);
 ctm_status ctm_corner_spectrum(ctm_ctx* c, int which, double* s, int cap, int* n);
 
 /* Replace beta and A and keep the converged environments as the starting
- * point of the next ctm_iterate (warm restart). */
+ * point of the next ctm_iterate (warm restart); max_iter of ctm_iterate(0)
+ * counts from here, and a reduced-precision context starts its
+ * reduced-precision phase again. */
 ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A);
 
 /* Iterations done so far, and the device bytes the context holds. */

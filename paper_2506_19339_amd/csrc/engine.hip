@@ -177,11 +177,16 @@ constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resi
 constexpr double kDefaultCutoff = 1e-8;
 constexpr int kJacobiSweeps = 40;
 constexpr int kMaxBatch = 16;       // projectors factorised together
+constexpr int kMaxIterateBatch = 64; // contexts advanced by one ctm_iterate_batch call
 // spectrum-change floors of the reduced-precision phases (rounding noise of
 // the FP32 / BF16 products keeps the change of the normalised spectrum above
 // roughly these values)
 constexpr double kLpTolFp32 = 1e-6;
 constexpr double kLpTolBf16 = 1e-3;
+// pseudo-inverse cutoffs of the reduced-precision phases (above the relative
+// rounding level of rho_B rho_T formed from FP32 / BF16 products)
+constexpr double kLpCutFp32 = 1e-7;
+constexpr double kLpCutBf16 = 1e-2;
 
 }  // namespace
 
@@ -692,7 +697,11 @@ struct Worker {
         svd_batch(rq);
         // each bond keeps the chi largest singular values that are above the
         // relative cutoff (its numerical rank): one small read-back for all
-        const double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : kDefaultCutoff;
+        double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : kDefaultCutoff;
+        // rho_B rho_T built from FP32 / BF16 products carries a relative error of
+        // order the unit roundoff; singular values below that level are noise
+        if (bulk == CTM_FP32) cut = std::max(cut, kLpCutFp32);
+        if (bulk == CTM_BF16) cut = std::max(cut, kLpCutBf16);
         for (size_t j = 0; j < rq.size(); ++j) ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut, icount + j);
         int rank[kMaxBatch] = {0};
         HIPCHK(hipMemcpyAsync(rank, icount, rq.size() * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -960,6 +969,7 @@ struct ctm_ctx {
     Worker w[2];                     // one per network
     hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     int iters = 0;
+    int base_iters = 0;              // iters at the last ctm_reset_tensor (max_iter counts from here)
     bool lp_done = false;            // reduced-precision phase over (FP64 refinement runs)
     std::string err;
 
@@ -1106,6 +1116,111 @@ static void sync_workers(ctm_ctx* c)
     for (auto& x : c->w) HIPCHK(hipStreamSynchronize(x.st));
 }
 
+// Moves of several contexts at once: in every move the two networks of every
+// active context step concurrently (one host thread each), then each context
+// checks its spectrum change.  n_iter <= 0: each context runs until its
+// spectrum change is below tol (with the reduced-precision phase logic) or
+// max_iter; n_iter < 0: the same rule for at most -n_iter moves (a slice of
+// the run, for schedulers); n_iter > 0: exactly n_iter moves.  Per-context
+// results in the arrays (may be NULL); the return value is the first non-OK
+// status.
+static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done, double* last_delta,
+                               int* converged, int* status)
+{
+    const bool until = n_iter <= 0;
+    std::vector<int> budget(n), done(n, 0);
+    std::vector<double> dl(n, 0.0);
+    std::vector<char> active(n, 0), conv(n, 0), capped(n, 0);
+    std::vector<int> st(n, CTM_OK);
+    for (int i = 0; i < n; ++i) {
+        ctm_ctx* c = cs[i];
+        const int left = std::max(0, c->cfg.max_iter - (c->iters - c->base_iters));
+        budget[i] = n_iter > 0 ? n_iter : (n_iter == 0 ? left : std::min(left, -n_iter));
+        capped[i] = until && budget[i] == left;   // the budget ends at max_iter
+        st[i] = guarded(c, [&] { c->fork(); });
+        active[i] = st[i] == CTM_OK && budget[i] > 0;
+    }
+    for (;;) {
+        std::vector<int> act;
+        for (int i = 0; i < n; ++i)
+            if (active[i]) act.push_back(i);
+        if (act.empty()) break;
+        // one move of every active context
+        std::vector<std::exception_ptr> ep(2 * act.size());
+        std::vector<std::thread> th;
+        auto task = [&](size_t a, int wi) {
+            ctm_ctx* c = cs[act[a]];
+            try {
+                const int64_t chi = (c->iters == 0) ? (int64_t)INT_MAX : (int64_t)c->chi;
+                const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;
+                Worker& W = c->w[wi];
+                W.bulk = prec;
+                W.step(c->net[wi], chi);
+                HIPCHK(hipGetLastError());
+            } catch (...) {
+                ep[2 * a + wi] = std::current_exception();
+            }
+        };
+        for (size_t a = 0; a < act.size(); ++a)
+            for (int wi = 0; wi < 2; ++wi)
+                if (a + wi > 0) th.emplace_back(task, a, wi);
+        task(0, 0);
+        for (auto& t : th) t.join();
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int i = act[a];
+            ctm_ctx* c = cs[i];
+            st[i] = guarded(c, [&] {
+                for (int wi = 0; wi < 2; ++wi)
+                    if (ep[2 * a + wi]) std::rethrow_exception(ep[2 * a + wi]);
+                const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;
+                ++c->iters;
+                ++done[i];
+                if (until || done[i] == budget[i]) {
+                    double h[2];
+                    for (int wi = 0; wi < 2; ++wi)
+                        HIPCHK(hipMemcpyAsync(&h[wi], c->net[wi].delta, sizeof(double), hipMemcpyDeviceToHost,
+                                              c->w[wi].st));
+                    sync_workers(c);
+                    dl[i] = std::max(h[0], h[1]);
+                    if (!std::isfinite(dl[i])) throw CtmError(CTM_ENUMERIC, "non-finite spectrum");
+                    if (until && c->iters > 1) {
+                        if (prec == CTM_FP64) {
+                            if (dl[i] < c->cfg.tol) conv[i] = 1;
+                        } else if (dl[i] < std::max(c->cfg.tol, c->lp_tol())) {
+                            // end of the reduced-precision phase: stop, or refine in FP64
+                            if (!c->cfg.refine) conv[i] = 1;
+                            else c->lp_done = true;
+                        } else if (c->cfg.refine && 2 * (c->iters - c->base_iters) >= c->cfg.max_iter) {
+                            // the reduced-precision phase gets at most half of max_iter
+                            c->lp_done = true;
+                        }
+                    }
+                }
+            });
+            if (st[i] != CTM_OK || conv[i] || done[i] >= budget[i]) active[i] = 0;
+        }
+    }
+    ctm_status first = CTM_OK;
+    for (int i = 0; i < n; ++i) {
+        ctm_ctx* c = cs[i];
+        const int s2 = guarded(c, [&] {
+            c->join();
+            HIPCHK(hipStreamSynchronize(c->ust));
+        });
+        if (st[i] == CTM_OK) st[i] = s2;
+        if (st[i] == CTM_OK && capped[i] && !conv[i]) {
+            c->err = "max_iter reached before tol";
+            st[i] = CTM_ENOCONV;
+        }
+        if (iters_done) iters_done[i] = done[i];
+        if (last_delta) last_delta[i] = dl[i];
+        if (converged) converged[i] = conv[i];
+        if (status) status[i] = st[i];
+        if (first == CTM_OK && st[i] != CTM_OK) first = (ctm_status)st[i];
+    }
+    return first;
+}
+
 extern "C" {
 
 int ctm_abi_version(void) { return CTM_ABI_VERSION; }
@@ -1183,51 +1298,23 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
 ctm_status ctm_iterate(ctm_ctx* c, int n_iter, int* iters_done, double* last_delta)
 {
     if (!c) return CTM_EINVAL;
-    int done = 0;
-    double dl = 0.0;
-    bool conv = false;
-    ctm_status s = guarded(c, [&] {
-        const bool until = n_iter <= 0;
-        const int budget = until ? std::max(0, c->cfg.max_iter - c->iters) : n_iter;
-        c->fork();
-        for (int it = 0; it < budget; ++it) {
-            // the first move from the product boundary never truncates
-            const int64_t chi = (c->iters == 0) ? (int64_t)INT_MAX : (int64_t)c->chi;
-            const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;
-            c->both([&](Worker& W, Net& N) {
-                W.bulk = prec;
-                W.step(N, chi);
-                HIPCHK(hipGetLastError());
-            });
-            ++c->iters;
-            ++done;
-            if (until || it == budget - 1) {
-                double h[2];
-                for (int i = 0; i < 2; ++i)
-                    HIPCHK(hipMemcpyAsync(&h[i], c->net[i].delta, sizeof(double), hipMemcpyDeviceToHost, c->w[i].st));
-                sync_workers(c);
-                dl = std::max(h[0], h[1]);
-                if (!std::isfinite(dl)) throw CtmError(CTM_ENUMERIC, "non-finite spectrum");
-                if (until && c->iters > 1) {
-                    if (prec == CTM_FP64) {
-                        if (dl < c->cfg.tol) { conv = true; break; }
-                    } else if (dl < std::max(c->cfg.tol, c->lp_tol())) {
-                        // end of the reduced-precision phase: stop, or refine in FP64
-                        if (!c->cfg.refine) { conv = true; break; }
-                        c->lp_done = true;
-                    }
-                }
-            }
-        }
-        c->join();
-        HIPCHK(hipStreamSynchronize(c->ust));
-    });
-    if (iters_done) *iters_done = done;
-    if (last_delta) *last_delta = dl;
-    if (s == CTM_OK && n_iter <= 0 && !conv) {
-        c->err = "max_iter reached before tol";
-        return CTM_ENOCONV;
+    int st = CTM_OK;
+    return iterate_many(&c, 1, n_iter, iters_done, last_delta, nullptr, &st);
+}
+
+ctm_status ctm_iterate_batch(ctm_ctx** cs, int n, int n_iter, int* iters_done, double* last_delta,
+                             int* converged, int* status)
+{
+    if (!cs || n < 1 || n > kMaxIterateBatch) return CTM_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!cs[i]) return CTM_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (cs[j] == cs[i]) return CTM_EINVAL;
     }
+    std::vector<int> st(n, CTM_OK);
+    const ctm_status s = iterate_many(cs, n, n_iter, iters_done, last_delta, converged, st.data());
+    if (status)
+        for (int i = 0; i < n; ++i) status[i] = st[i];
     return s;
 }
 
@@ -1310,6 +1397,7 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A)
         load_tensor(c, beta, A);
         c->join();
         c->lp_done = false;
+        c->base_iters = c->iters;
     });
 }
 

@@ -55,6 +55,9 @@ def load_library(path=None):
     vp = ctypes.c_void_p
     lib.ctm_init.argtypes = [ctypes.POINTER(_Config), ctypes.c_double, vp, vp, ctypes.POINTER(vp)]
     lib.ctm_iterate.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
+    lib.ctm_iterate_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), dp, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]
     lib.ctm_free_energy.argtypes = [vp, dp, dp, dp]
     lib.ctm_grad.argtypes = [vp, vp]
     lib.ctm_corner_spectrum.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
@@ -69,7 +72,7 @@ def load_library(path=None):
     lib.ctm_status_string.argtypes = [ctypes.c_int]
     lib.ctm_status_string.restype = ctypes.c_char_p
     lib.ctm_abi_version.restype = ctypes.c_int
-    for fn in ("ctm_init", "ctm_iterate", "ctm_free_energy", "ctm_grad", "ctm_corner_spectrum",
+    for fn in ("ctm_init", "ctm_iterate", "ctm_iterate_batch", "ctm_free_energy", "ctm_grad", "ctm_corner_spectrum",
                "ctm_reset_tensor", "ctm_query"):
         getattr(lib, fn).restype = ctypes.c_int
     if path is None:
@@ -197,3 +200,25 @@ class SplitCTM:
 
     def __exit__(self, *a):
         self.close()
+
+
+def iterate_batch(contexts, n_iter=0, lib=None):
+    """Advance several SplitCTM contexts together (ctm_iterate_batch): one move
+    of every still-active context per step, the networks of all of them
+    running concurrently.  n_iter as in ``SplitCTM.iterate`` (negative: a
+    slice of at most -n_iter moves with the stopping rule).  Returns
+    [(iters_done, last_delta, converged, status)] per context; raises only for
+    argument errors (CTM_EINVAL)."""
+    n = len(contexts)
+    if n == 0:
+        return []
+    lib = lib or contexts[0]._lib
+    arr = (ctypes.c_void_p * n)(*[c._ctx.value for c in contexts])
+    done = (ctypes.c_int * n)()
+    dl = (ctypes.c_double * n)()
+    cv = (ctypes.c_int * n)()
+    st = (ctypes.c_int * n)()
+    s = lib.ctm_iterate_batch(arr, n, int(n_iter), done, dl, cv, st)
+    if s == 1:
+        raise CtmError(s, "ctm_iterate_batch: invalid arguments")
+    return [(done[i], dl[i], bool(cv[i]), st[i]) for i in range(n)]

@@ -1,0 +1,67 @@
+"""Serving form: continuous batching of f-and-gradient requests on one GPU.
+
+Each request's result must be the same alone and in the mix: with cold starts
+bitwise (every request has its own context and streams, and every kernel is
+deterministic), with warm starts within the tolerance implied by the
+convergence criterion for the requests that converged."""
+import numpy as np
+import pytest
+
+from paper_2506_19339_amd import ctm, serving
+
+pytestmark = pytest.mark.gpu
+
+TOL, MAX_IT = 1e-9, 150
+
+
+def _alone(req):
+    import torch
+    A = torch.from_numpy(req.A).cuda()
+    with ctm.SplitCTM(req.beta, A, req.chi, max_iter=MAX_IT, tol=TOL) as c:
+        done, delta, conv = c.iterate(0)
+        f = c.free_energy()[0]
+        g = torch.empty_like(A)
+        c.grad(g)
+    return f, g.cpu().numpy(), done, conv
+
+
+def test_results_alone_and_in_the_mix_cold():
+    reqs = serving.trace_requests(8, 50.0, D_set=[2, 3], chi_set=[16, 24])
+    srv = serving.Server(max_slots=4, tol=TOL, max_iter=MAX_IT, warm=False)
+    stats = srv.run(reqs, realtime=True)
+    srv.close()
+    s = stats.summary()
+    assert s["requests"] == len(reqs) and s["max_active"] >= 2
+    assert np.isfinite(s["p50_latency_s"]) and s["p99_latency_s"] >= s["p50_latency_s"]
+    for r in reqs:
+        f, g, done, conv = _alone(r)
+        assert r.status in (0, ctm.CTM_ENOCONV)
+        assert r.iters == done
+        assert r.f == f
+        assert np.array_equal(r.g, g)
+
+
+def test_warm_starts_agree_with_cold_results():
+    reqs = serving.trace_requests(8, 50.0, D_set=[2, 3], chi_set=[16, 24])
+    srv = serving.Server(max_slots=2, tol=TOL, max_iter=MAX_IT, warm=True)
+    stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert stats.warm_starts > 0
+    for r in reqs:
+        if r.status != 0:
+            continue
+        f, g, done, conv = _alone(r)
+        if not conv:
+            continue
+        assert abs(r.f - f) <= 1e-7 * abs(f), (r.rid, r.warm, r.f, f)
+        assert np.linalg.norm(r.g - g) <= 1e-4 * np.linalg.norm(g)
+
+
+def test_admission_respects_the_memory_budget():
+    """A budget that holds one context at a time serialises the requests."""
+    reqs = serving.trace_requests(4, 100.0, D_set=[2], chi_set=[16])
+    one = serving.footprint_model(2, 16)
+    srv = serving.Server(hbm_budget=int(1.5 * one), max_slots=8, tol=TOL, max_iter=40, warm=False)
+    stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert stats.max_active == 1 and stats.n_done == 4
