@@ -32,14 +32,15 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 
 # kernel classes timed by the library's profile mode: name, roofline bound, peak
 KERNEL_CLASSES = {
     0: ("gemm_f64_kernel (v_mfma_f64_16x16x4, split-K reduction included)", "mfma", PEAK_FP64_MFMA_TFLOPS),
-    1: ("jacobi_svd_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
-    2: ("cholqr_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
+    1: ("jacobi_reg_kernel / jacobi_svd_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
+    2: ("cholqr_reg_kernel / cholqr_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
+    3: ("gemm_lp_kernel (FP32 / BF16 MFMA)", "mfma", 157.3),
 }
 
 
-def gpu_eval(ctm, torch, w, A, g, stream, profile=False):
+def gpu_eval(ctm, torch, w, A, g, stream, profile=False, precision=0):
     c = ctm.SplitCTM(w["beta"], A, w["chi"], max_iter=w["max_iter"], tol=w["tol"],
-                     stream=stream, profile=profile)
+                     stream=stream, profile=profile, precision=precision)
     done, delta, conv = c.iterate(0)
     f, lk3, lk2 = c.free_energy()
     c.grad(g)
@@ -75,6 +76,7 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--no-fp32-leg", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
@@ -136,6 +138,27 @@ def main():
                                                             tflops=(v[2] / (v[1] / 1e3) / 1e12) if v[1] > 0 else None)
                                  for k, v in stats.items()})
 
+    fp32 = None
+    if not args.no_fp32_leg:
+        # reduced-precision form: FP32 products / FP32 accumulation in the bulk
+        # contractions, FP64 projectors, spectrum, f and g (same workload)
+        print("fp32 leg", file=sys.stderr, flush=True)
+        c, _ = gpu_eval(ctm, torch, w, A, g, sp, precision=ctm.CTM_FP32)
+        c.close()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it32 = []
+        for i in range(args.steps):
+            c, info32 = gpu_eval(ctm, torch, w, A, g, sp, precision=ctm.CTM_FP32)
+            it32.append(info32["iters"])
+            c.close()
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t1
+        fp32 = dict(evals_per_s=args.steps / el32, ms_per_step=1e3 * el32 / args.steps,
+                    iters_per_eval=float(np.mean(it32)), f=info32["f"],
+                    rel_f_vs_fp64=abs(info32["f"] - info["f"]) / abs(info["f"]),
+                    speedup_vs_fp64=(args.steps / el32) / evals_per_s)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -170,6 +193,7 @@ def main():
         "iters_per_eval": float(np.mean(iters)),
         "f": info["f"],
         "roofline": roofline,
+        "fp32_form": fp32,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

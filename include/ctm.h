@@ -64,17 +64,23 @@ typedef enum {
     CTM_FP32 = 1,       /* bulk contractions float32 products / float32 accumulate */
     CTM_BF16 = 2        /* bulk contractions bfloat16 products / float32 accumulate */
 } ctm_precision;
-/* In the reduced-precision forms the bulk contractions of a move (absorption,
- * projector environments rho_B rho_T, application of the projectors) run on
- * the FP32 or BF16 matrix cores with FP32 accumulation; the projector
- * factorisations, the corner spectrum, the normalisations and f and g stay
- * FP64.  Tensors are stored in FP64 throughout (operands are rounded when
- * they are staged for the matrix cores).  During the reduced-precision phase
- * the relative pseudo-inverse cutoff is raised to the rounding level of the
- * products (1e-7 FP32, 1e-2 BF16).  The phase ends when the spectrum change
- * drops below max(tol, lp_tol); with refine = 1 the iteration then continues
- * in FP64 (with svd_cutoff) until the change is below tol, and the phase also
- * ends once half of max_iter is spent. */
+/* In the reduced-precision forms the bulk contractions of a move of the
+ * triple-layer network (the layer-by-layer absorption that builds the
+ * corners, edges and the projector environments rho_T, rho_B, and the
+ * renormalisation with the projectors) run on the FP32 or BF16 matrix cores
+ * with FP32 accumulation; the double-layer (norm) network, the cheaper one
+ * and the one whose environment is the more sensitive to rounding, stays
+ * FP64.  The projector
+ * construction -- the product rho_B rho_T, its factorisation and the
+ * application of V S^-1/2 and S^-1/2 U^T -- the corner spectrum, the
+ * normalisations and f and g stay FP64.  Tensors are stored in FP64
+ * throughout (operands are rounded when they are staged for the matrix
+ * cores).  During the reduced-precision phase the relative pseudo-inverse
+ * cutoff is raised to the rounding level of the products (1e-7 FP32, 1e-3
+ * BF16).  The phase ends when the spectrum change drops below
+ * max(tol, lp_tol); with refine = 1 the iteration then continues in FP64
+ * (with svd_cutoff) until the change is below tol, and the phase also ends
+ * once a quarter of max_iter is spent. */
 
 #define CTM_FLAG_DEVICE_PTRS 1
 #define CTM_FLAG_PROFILE 2      /* record HIP events around GEMM / Jacobi launches */
@@ -89,7 +95,7 @@ typedef struct {
     int power_iters;    /* subspace iterations of the projector SVD (0: default)  */
     double svd_cutoff;  /* relative singular-value cutoff (0: default 1e-8)       */
     double lp_tol;      /* end of the reduced-precision phase (0: 1e-6 FP32,      */
-                        /* 1e-3 BF16); ignored for CTM_FP64                       */
+                        /* 1e-2 BF16); ignored for CTM_FP64                       */
     int refine;         /* 1: continue in FP64 to tol after that phase            */
 } ctm_config;
 

@@ -182,11 +182,11 @@ constexpr int kMaxIterateBatch = 64; // contexts advanced by one ctm_iterate_bat
 // the FP32 / BF16 products keeps the change of the normalised spectrum above
 // roughly these values)
 constexpr double kLpTolFp32 = 1e-6;
-constexpr double kLpTolBf16 = 1e-3;
+constexpr double kLpTolBf16 = 1e-2;
 // pseudo-inverse cutoffs of the reduced-precision phases (above the relative
 // rounding level of rho_B rho_T formed from FP32 / BF16 products)
 constexpr double kLpCutFp32 = 1e-7;
-constexpr double kLpCutBf16 = 1e-2;
+constexpr double kLpCutBf16 = 1e-3;
 
 }  // namespace
 
@@ -211,6 +211,7 @@ struct Worker {
     int64_t exact_min = kJacobiExact, exact_area = kJacobiExactArea;
     int64_t trace_perm = 0;          // testing aid: log permutes of at least this many elements
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
+    double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
     int cur = CTM_FP64;              // precision of the GEMMs issued now
     bool profiling = false;
     KStat kstat[4];                  // [0] FP64 GEMM, [1] Jacobi SVD, [2] Cholesky QR, [3] FP32/BF16 GEMM
@@ -688,7 +689,12 @@ struct Worker {
                 continue;
             }
             SvdReq r;
-            r.M = mm(rB, false, rT, false);          // remB x remT
+            {
+                // rho_B rho_T in FP64 in every form: its small singular values
+                // (down to ~1e-7 of the largest) decide the projectors
+                Prec fp64(*this, CTM_FP64);
+                r.M = mm(rB, false, rT, false);      // remB x remT
+            }
             r.kk = std::min<int64_t>(chi, std::min(remB, remT));
             rq.push_back(r);
             of.push_back(i);
@@ -700,12 +706,15 @@ struct Worker {
         double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : kDefaultCutoff;
         // rho_B rho_T built from FP32 / BF16 products carries a relative error of
         // order the unit roundoff; singular values below that level are noise
-        if (bulk == CTM_FP32) cut = std::max(cut, kLpCutFp32);
-        if (bulk == CTM_BF16) cut = std::max(cut, kLpCutBf16);
+        if (bulk == CTM_FP32) cut = std::max(cut, lp_cut > 0 ? lp_cut : kLpCutFp32);
+        if (bulk == CTM_BF16) cut = std::max(cut, lp_cut > 0 ? lp_cut : kLpCutBf16);
         for (size_t j = 0; j < rq.size(); ++j) ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut, icount + j);
         int rank[kMaxBatch] = {0};
         HIPCHK(hipMemcpyAsync(rank, icount, rq.size() * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        // P_B = rho_T V S^-1/2 and P_T = S^-1/2 U^T rho_B amplify the directions
+        // of small singular values: FP64 in every form
+        Prec fp64(*this, CTM_FP64);
         for (size_t j = 0; j < rq.size(); ++j) {
             const size_t i = of[j];
             const Tn &rT = prs[i].first, &rB = prs[i].second;
@@ -1152,7 +1161,10 @@ static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done,
             ctm_ctx* c = cs[act[a]];
             try {
                 const int64_t chi = (c->iters == 0) ? (int64_t)INT_MAX : (int64_t)c->chi;
-                const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;
+                // the reduced-precision forms apply to the triple-layer network;
+                // the norm network stays FP64 (it is cheaper, and its
+                // environment can be far more sensitive to rounding)
+                const int prec = (c->lp_done || wi == 1) ? CTM_FP64 : c->cfg.precision;
                 Worker& W = c->w[wi];
                 W.bulk = prec;
                 W.step(c->net[wi], chi);
@@ -1172,7 +1184,7 @@ static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done,
             st[i] = guarded(c, [&] {
                 for (int wi = 0; wi < 2; ++wi)
                     if (ep[2 * a + wi]) std::rethrow_exception(ep[2 * a + wi]);
-                const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;
+                const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;   // of the triple layer
                 ++c->iters;
                 ++done[i];
                 if (until || done[i] == budget[i]) {
@@ -1190,8 +1202,8 @@ static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done,
                             // end of the reduced-precision phase: stop, or refine in FP64
                             if (!c->cfg.refine) conv[i] = 1;
                             else c->lp_done = true;
-                        } else if (c->cfg.refine && 2 * (c->iters - c->base_iters) >= c->cfg.max_iter) {
-                            // the reduced-precision phase gets at most half of max_iter
+                        } else if (c->cfg.refine && 4 * (c->iters - c->base_iters) >= c->cfg.max_iter) {
+                            // the reduced-precision phase gets at most a quarter of max_iter
                             c->lp_done = true;
                         }
                     }
@@ -1275,6 +1287,7 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
                 x.exact_area = x.exact_min * x.exact_min * 4;
             }
             if (const char* e = std::getenv("CTM_TRACE_PERMUTE")) x.trace_perm = std::atoll(e);   // testing aid
+            if (const char* e = std::getenv("CTM_LP_CUTOFF")) x.lp_cut = std::atof(e);            // testing aid
         }
         HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         for (auto& e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));

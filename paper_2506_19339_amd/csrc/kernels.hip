@@ -956,6 +956,25 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
 typedef __attribute__((address_space(1))) double gdouble;
 constexpr int kSmallJacobi = 128;
 
+// v from lane l ^ pattern of the DPP control CTRL (all 64 lanes active), FP64
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// sum over each aligned group of 16 lanes, result in every lane of the group:
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
+__device__ inline double sum16(double v)
+{
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    return v;
+}
+
 template <bool WL>
 __global__ __launch_bounds__(1024) void jacobi_small_kernel(JacobiBatch jobs, int max_sweeps)
 {
@@ -1035,13 +1054,10 @@ __global__ __launch_bounds__(1024) void jacobi_small_kernel(JacobiBatch jobs, in
                     ga += a[u] * b[u];
                 }
             }
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1) {
-                al += __shfl_xor(al, o, 16);
-                be += __shfl_xor(be, o, 16);
-                ga += __shfl_xor(ga, o, 16);
-            }
-            if (active && ga != 0.0 && al > noise2 && be > noise2 && fabs(ga) > tol * sqrt(al * be)) {
+            al = sum16(al);
+            be = sum16(be);
+            ga = sum16(ga);
+            if (active && ga != 0.0 && al > noise2 && be > noise2 && ga * ga > tol * tol * (al * be)) {
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
@@ -1107,6 +1123,252 @@ __global__ __launch_bounds__(1024) void jacobi_small_kernel(JacobiBatch jobs, in
     for (int j = tid; j < n; j += nthr) jb.S[rnk[j]] = sig[j];
 }
 
+// Register-resident one-sided Jacobi for m, n <= 128 with the odd-even
+// (transposition) ordering.  The n columns (a zero column is added when n is
+// odd) sit at positions 0 .. ne-1; step s pairs positions (2p, 2p+1) when s is
+// even and (2p+1, 2p+2) when s is odd, rotates each pair and swaps the two
+// columns' positions.  After ne steps the order is reversed and every pair has
+// met once (odd-even transposition sort of a reversed sequence), so a sweep is
+// ne steps.  Pair p is held in registers by 16 lanes: lanes 0-7 hold 16 rows
+// each of its two columns of X, lanes 8-15 16 rows each of its two columns of
+// V.  A 512-thread workgroup gives each 16-lane group two pairs (p and p + 32),
+// so that the 128 doubles a lane holds fit in registers.  Between steps each
+// pair hands one column to a neighbour through LDS: per step half of the
+// columns move and nothing else touches memory.
+constexpr int kRegJacobi = 128;
+constexpr int kRegThreads = 512;
+
+template <bool WANT_V>
+__global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch jobs, int max_sweeps)
+{
+    constexpr int NP = kRegJacobi / 2;             // pairs
+    constexpr int NG = kRegThreads / 16;           // 16-lane groups
+    constexpr int PP = NP / NG;                    // pairs per group
+    __shared__ __attribute__((aligned(16))) double xfer[NP][2 * kRegJacobi];
+    __shared__ __attribute__((aligned(16))) double park[2 * kRegJacobi];
+    __shared__ int xid[NP];
+    __shared__ int park_id;
+    __shared__ double sig[kRegJacobi + 1];
+    __shared__ int rnk[kRegJacobi + 1];
+    __shared__ double gsum[NG];
+    __shared__ int rotated;
+    __shared__ double fro2;
+    const JacobiJob jb = jobs.job[blockIdx.x];
+    const int m = jb.m, n = jb.n;
+    const int ne = n + (n & 1);
+    const int P = ne / 2;
+    const int tid = threadIdx.x, g = tid >> 4, l16 = tid & 15, half = l16 >> 3, sub = l16 & 7;
+    const int rows = half == 0 ? m : n;      // rows of the part this lane holds
+
+    double a[PP][16], b[PP][16];
+    int ia[PP], ib[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        const int pr = g + NG * q;
+        ia[q] = 2 * pr;
+        ib[q] = 2 * pr + 1;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int r = sub + 8 * u;
+            double va = 0.0, vb = 0.0;
+            if (pr < P && r < rows) {
+                if (half == 0) {
+                    va = ia[q] < n ? jb.X[(int64_t)ia[q] * m + r] : 0.0;
+                    vb = ib[q] < n ? jb.X[(int64_t)ib[q] * m + r] : 0.0;
+                } else if (WANT_V) {
+                    va = (r == ia[q]) ? 1.0 : 0.0;
+                    vb = (r == ib[q]) ? 1.0 : 0.0;
+                }
+            }
+            a[q][u] = va;
+            b[q][u] = vb;
+        }
+    }
+    {
+        double t = 0.0;
+        if (half == 0)
+#pragma unroll
+            for (int q = 0; q < PP; ++q)
+#pragma unroll
+                for (int u = 0; u < 16; ++u) t += a[q][u] * a[q][u] + b[q][u] * b[q][u];
+        t = sum16(t);
+        if (l16 == 0) gsum[g] = t;
+        __syncthreads();
+        if (tid == 0) {
+            double f = 0.0;
+            for (int i = 0; i < NG; ++i) f += gsum[i];
+            fro2 = f;
+        }
+        __syncthreads();
+    }
+    const double noise2 = 1e-30 * fro2;
+    const double tol = 2.0 * sqrt((double)m) * 2.220446049250313e-16;
+    const double tol2 = tol * tol;
+
+    // rotation of the pairs held in (L, R), then swap of their positions:
+    // L <- s L + c R, R <- c L - s R; lid / rid follow the columns
+    auto rotate = [&](double (&L)[PP][16], double (&R)[PP][16], int (&lid)[PP], int (&rid)[PP], bool odd) {
+        double al[PP], be[PP], ga[PP];
+#pragma unroll
+        for (int q = 0; q < PP; ++q) {
+            al[q] = be[q] = ga[q] = 0.0;
+            if (half == 0) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    al[q] += L[q][u] * L[q][u];
+                    be[q] += R[q][u] * R[q][u];
+                    ga[q] += L[q][u] * R[q][u];
+                }
+            }
+            al[q] = sum16(al[q]);
+            be[q] = sum16(be[q]);
+            ga[q] = sum16(ga[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < PP; ++q) {
+            const int pr = g + NG * q;
+            if (!(pr < P && (!odd || pr < P - 1))) continue;
+            double c = 1.0, sn = 0.0;
+            if (ga[q] != 0.0 && al[q] > noise2 && be[q] > noise2 && ga[q] * ga[q] > tol2 * (al[q] * be[q])) {
+                const double zeta = (be[q] - al[q]) / (2.0 * ga[q]);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                c = 1.0 / sqrt(1.0 + t * t);
+                sn = c * t;
+                if (l16 == 0) rotated = 1;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const double x = L[q][u], y = R[q][u];
+                L[q][u] = sn * x + c * y;
+                R[q][u] = c * x - sn * y;
+            }
+            const int t = lid[q];
+            lid[q] = rid[q];
+            rid[q] = t;
+        }
+    };
+
+    // Registers a and b trade roles between the two halves of a double step:
+    // even step: left = a (position 2p), right = b (2p+1); the column at 2p
+    // leaves and the one at 2p+2 arrives into a, so the odd step has left = b
+    // (2p+1), right = a (2p+2); then the column at 2p+2 leaves and the one at
+    // 2p arrives into a, restoring the even-step roles.
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int step = 0; step < ne; step += 2) {
+            rotate(a, b, ia, ib, false);
+            // even -> odd: send position 2p (a) to p-1 (p = 0: park), receive 2p+2 into a
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                const int pr = g + NG * q;
+                if (pr >= P) continue;
+                double* dst = pr == 0 ? park : xfer[pr];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) dst[half * kRegJacobi + sub + 8 * u] = a[q][u];
+                if (l16 == 0) {
+                    if (pr == 0) park_id = ia[q];
+                    else xid[pr] = ia[q];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                const int pr = g + NG * q;
+                if (pr >= P) continue;
+                if (pr + 1 < P) {
+                    const double* srcp = xfer[pr + 1];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) a[q][u] = srcp[half * kRegJacobi + sub + 8 * u];
+                    ia[q] = xid[pr + 1];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) a[q][u] = 0.0;
+                    ia[q] = -1;
+                }
+            }
+            __syncthreads();
+            rotate(b, a, ib, ia, true);
+            // odd -> even: send position 2p+2 (a) to p+1, receive 2p into a (p = 0: park)
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                const int pr = g + NG * q;
+                if (pr + 1 >= P) continue;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) xfer[pr][half * kRegJacobi + sub + 8 * u] = a[q][u];
+                if (l16 == 0) xid[pr] = ia[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                const int pr = g + NG * q;
+                if (pr >= P) continue;
+                const double* srcp = pr == 0 ? park : xfer[pr - 1];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) a[q][u] = srcp[half * kRegJacobi + sub + 8 * u];
+                ia[q] = pr == 0 ? park_id : xid[pr - 1];
+            }
+            __syncthreads();
+        }
+        if (rotated == 0) {
+            if (jb.sweeps && tid == 0) jb.sweeps[0] = sweep + 1;
+            break;
+        }
+        __syncthreads();
+        if (sweep + 1 == max_sweeps && jb.sweeps && tid == 0) jb.sweeps[0] = max_sweeps;
+    }
+    // singular values = column norms, by original column id (the padding column has id n)
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        const int pr = g + NG * q;
+        double na = 0.0, nb = 0.0;
+        if (half == 0)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                na += a[q][u] * a[q][u];
+                nb += b[q][u] * b[q][u];
+            }
+        na = sum16(na);
+        nb = sum16(nb);
+        if (pr < P && l16 == 0) {
+            if (ia[q] >= 0 && ia[q] < n) sig[ia[q]] = sqrt(na);
+            if (ib[q] >= 0 && ib[q] < n) sig[ib[q]] = sqrt(nb);
+        }
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) {
+        int r = 0;
+        const double sj = sig[j];
+        for (int i = 0; i < n; ++i) {
+            const double si = sig[i];
+            r += (si > sj) || (si == sj && i < j);
+        }
+        rnk[j] = r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        const int pr = g + NG * q;
+        if (pr >= P) continue;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int id = side == 0 ? ia[q] : ib[q];
+            if (id < 0 || id >= n) continue;
+            const int dst = rnk[id];
+            const double sj = sig[id];
+            const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int r = sub + 8 * u;
+                const double v = side == 0 ? a[q][u] : b[q][u];
+                if (half == 0 && r < m) jb.U[(int64_t)dst * m + r] = v * inv;
+                if (WANT_V && half == 1 && r < n) jb.V[(int64_t)dst * n + r] = v;
+            }
+            if (l16 == 0) jb.S[dst] = sj;
+        }
+    }
+}
+
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
 {
     if (jobs.n <= 0) return;
@@ -1122,7 +1384,17 @@ void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
         need_x = std::max(need_x, mn);
         need_w = std::max(need_w, mn + nn);
     }
-    if (small && wl)
+    bool any_v = false, all_v = true;
+    for (int i = 0; i < jobs.n; ++i) {
+        any_v = any_v || jobs.job[i].want_v;
+        all_v = all_v && jobs.job[i].want_v;
+    }
+    if (small && (all_v || !any_v)) {
+        if (all_v)
+            hipLaunchKernelGGL((jacobi_reg_kernel<true>), dim3(jobs.n), dim3(kRegThreads), 0, s, jobs, max_sweeps);
+        else
+            hipLaunchKernelGGL((jacobi_reg_kernel<false>), dim3(jobs.n), dim3(kRegThreads), 0, s, jobs, max_sweeps);
+    } else if (small && wl)
         hipLaunchKernelGGL((jacobi_small_kernel<true>), dim3(jobs.n), dim3(1024), need_w * sizeof(double), s, jobs, max_sweeps);
     else if (small)
         hipLaunchKernelGGL((jacobi_small_kernel<false>), dim3(jobs.n), dim3(1024), need_x * sizeof(double), s, jobs, max_sweeps);

@@ -180,14 +180,18 @@ class Server:
                     continue
                 req.status = st
                 if st in (0, ctm.CTM_ENOCONV):
-                    req.f = c.free_energy()[0]
-                    if self.device_tensors:
-                        import torch
-                        g = torch.empty_like(A)
-                        c.grad(g)
-                        req.g = g.cpu().numpy()
-                    else:
-                        req.g = c.grad()
+                    try:
+                        req.f = c.free_energy()[0]
+                        if self.device_tensors:
+                            import torch
+                            g = torch.empty_like(A)
+                            c.grad(g)
+                            req.g = g.cpu().numpy()
+                        else:
+                            req.g = c.grad()
+                    except ctm.CtmError as e:   # e.g. a negative network value
+                        req.status = e.status
+                        st = e.status
                 req.t_done = now()
                 stats.latencies.append(req.latency)
                 stats.n_done += 1
