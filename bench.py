@@ -31,16 +31,37 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 
 
 # kernel classes timed by the library's profile mode: name, roofline bound, peak
 KERNEL_CLASSES = {
-    0: ("gemm_f64_kernel (v_mfma_f64_16x16x4, split-K reduction included)", "mfma", PEAK_FP64_MFMA_TFLOPS),
+    0: ("gemm_f64_kernel (v_mfma_f64_16x16x4)", "mfma", PEAK_FP64_MFMA_TFLOPS),
     1: ("jacobi_reg_kernel / jacobi_svd_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
     2: ("cholqr_reg_kernel / cholqr_kernel", "alu", PEAK_FP64_VECTOR_TFLOPS),
     3: ("gemm_lp_kernel (FP32 / BF16 MFMA)", "mfma", 157.3),
+    4: ("gemm_reduce_kernel (split-K)", "hbm", None),
 }
 
 
-def gpu_eval(ctm, torch, w, A, g, stream, profile=False, precision=0):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d5_chi100_traffic.json")
+KERNELS_SRC = os.path.join(ROOT, "paper_2506_19339_amd", "csrc", "kernels.hip")
+TRAFFIC_KEY = {0: "gemm_f64_kernel", 1: "jacobi_reg_kernel", 2: "cholqr_reg_kernel"}
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of the kernel class from the FETCH_SIZE / WRITE_SIZE
+    counter runs recorded in profiles/ (scaled by the copy calibration), or
+    None when they were taken with other kernel source than the current one."""
+    import hashlib
+    try:
+        data = json.load(open(TRAFFIC_FILE))
+        cur = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if data.get("kernels_hip_sha256") != cur or TRAFFIC_KEY.get(cls) not in data["kernels"]:
+        return None
+    return data["kernels"][TRAFFIC_KEY[cls]]["hbm_bytes_per_launch"]
+
+
+def gpu_eval(ctm, torch, w, A, g, stream, profile=False, precision=0, refine=False):
     c = ctm.SplitCTM(w["beta"], A, w["chi"], max_iter=w["max_iter"], tol=w["tol"],
-                     stream=stream, profile=profile, precision=precision)
+                     stream=stream, profile=profile, precision=precision, refine=refine)
     done, delta, conv = c.iterate(0)
     f, lk3, lk2 = c.free_energy()
     c.grad(g)
@@ -77,7 +98,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy three times (the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
               "(independent evaluations would shard one per GPU)", file=sys.stderr)
@@ -126,16 +159,19 @@ def main():
         stats = {k: c.kernel_stats(k) for k in KERNEL_CLASSES}
         c.close()
         total_ms = sum(v[1] for v in stats.values())
-        dom = max(stats, key=lambda k: stats[k][1])
+        dom = max((k for k in stats if KERNEL_CLASSES[k][2] is not None), key=lambda k: stats[k][1])
         name, bound, peak = KERNEL_CLASSES[dom]
-        launches, kms, kfl = stats[dom]
+        launches, kms, kfl, kby = stats[dom]
         ach = kfl / (kms / 1e3) / 1e12 if kms > 0 else None
         roofline = dict(kernel=name, bound=bound, achieved=ach, peak=peak, unit="TFLOP/s",
-                        frac=(ach / peak) if ach is not None else None, traffic=None,
+                        frac=(ach / peak) if ach is not None else None,
+                        traffic=measured_traffic(dom),
+                        algorithmic_bytes_per_launch=kby / max(launches, 1),
+                        algorithmic_flops_per_launch=kfl / max(launches, 1),
                         launches=launches, avg_launch_us=1e3 * kms / max(launches, 1),
                         share_of_kernel_time=kms / total_ms if total_ms > 0 else None,
                         classes={KERNEL_CLASSES[k][0]: dict(launches=v[0], ms=v[1],
-                                                            tflops=(v[2] / (v[1] / 1e3) / 1e12) if v[1] > 0 else None)
+                                                            tflops=(v[2] / (v[1] / 1e3) / 1e12) if v[1] > 0 and v[2] > 0 else None)
                                  for k, v in stats.items()})
 
     fp32 = None
@@ -143,13 +179,13 @@ def main():
         # reduced-precision form: FP32 products / FP32 accumulation in the bulk
         # contractions, FP64 projectors, spectrum, f and g (same workload)
         print("fp32 leg", file=sys.stderr, flush=True)
-        c, _ = gpu_eval(ctm, torch, w, A, g, sp, precision=ctm.CTM_FP32)
+        c, _ = gpu_eval(ctm, torch, w, A, g, sp, precision=ctm.CTM_FP32, refine=True)
         c.close()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         it32 = []
         for i in range(args.steps):
-            c, info32 = gpu_eval(ctm, torch, w, A, g, sp, precision=ctm.CTM_FP32)
+            c, info32 = gpu_eval(ctm, torch, w, A, g, sp, precision=ctm.CTM_FP32, refine=True)
             it32.append(info32["iters"])
             c.close()
         torch.cuda.synchronize()

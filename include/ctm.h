@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CTM_ABI_VERSION 2
+#define CTM_ABI_VERSION 3
 
 typedef struct ctm_ctx ctm_ctx;
 
@@ -157,14 +157,17 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A);
 ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes);
 
 /* Launch statistics of a context built with CTM_FLAG_PROFILE: which = 0 the
- * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernel, 2 the Cholesky QR kernel,
- * 3 the FP32 / BF16 MFMA GEMM kernel.
+ * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernels, 2 the Cholesky QR kernels,
+ * 3 the FP32 / BF16 MFMA GEMM kernel, 4 the split-K reduction of the GEMMs.
  * launches, summed kernel time in ms (HIP events on the context's streams
  * around each launch; the two network streams may overlap) and algorithmic
- * flops: 2 M N K per GEMM (both GEMM classes); per Jacobi sweep and column pair 12 m (+ 6 n with V);
- * 2 k^3 / 3 per Cholesky-QR factor.  Synchronises.  Any output may be NULL.
- * CTM_ESTATE without CTM_FLAG_PROFILE. */
-ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops);
+ * flops: 2 M N K per GEMM; per Jacobi sweep and column pair 12 m (+ 6 n with
+ * V); 2 k^3 / 3 per Cholesky-QR factor; none for the reduction.  bytes: the
+ * algorithmic operand and result bytes, 8 (M K + K N + M N) per GEMM (0 for
+ * the other classes).  Synchronises.  Any output may be NULL.  CTM_ESTATE
+ * without CTM_FLAG_PROFILE. */
+ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops,
+                            double* bytes);
 
 /* Release a context.  NULL-safe. */
 void ctm_destroy(ctm_ctx* c);

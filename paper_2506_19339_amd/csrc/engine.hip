@@ -162,6 +162,7 @@ struct Net {
 struct KStat {
     int64_t launches = 0;
     double flops = 0.0;
+    double bytes = 0.0;              // algorithmic operand + result bytes
     double ms = 0.0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 };
@@ -214,7 +215,8 @@ struct Worker {
     double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
     int cur = CTM_FP64;              // precision of the GEMMs issued now
     bool profiling = false;
-    KStat kstat[4];                  // [0] FP64 GEMM, [1] Jacobi SVD, [2] Cholesky QR, [3] FP32/BF16 GEMM
+    KStat kstat[5];                  // [0] FP64 GEMM, [1] Jacobi SVD, [2] Cholesky QR, [3] FP32/BF16 GEMM,
+                                     // [4] split-K reduction
     std::vector<hipEvent_t> ev_pool;
     // profile mode: sweeps of every Jacobi job, for its algorithmic flop count
     static constexpr int kSweepSlots = 4096;
@@ -317,13 +319,25 @@ struct Worker {
               int64_t sC, int64_t nb)
     {
         hipEvent_t e = prof_begin();
+        hipEvent_t mid = profiling ? ev_get() : nullptr;
         if (cur == CTM_FP64)
             ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, (int)nb,
-                           gws, gws_cap);
+                           gws, gws_cap, mid);
         else
             ctmk::gemm_lp(st, cur, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC,
-                          (int)nb, gws, gws_cap);
-        prof_end(cur == CTM_FP64 ? 0 : 3, e, 2.0 * (double)M * (double)N * (double)K * (double)nb);
+                          (int)nb, gws, gws_cap, mid);
+        if (profiling) {
+            // product kernel [e, mid], split-K reduction [mid, end]
+            const int cls = cur == CTM_FP64 ? 0 : 3;
+            kstat[cls].launches += 1;
+            kstat[cls].flops += 2.0 * (double)M * (double)N * (double)K * (double)nb;
+            kstat[cls].bytes += 8.0 * ((double)M * K + (double)K * N + (double)M * N) * (double)nb;
+            kstat[cls].pending.push_back({e, mid});
+            hipEvent_t end = ev_get();
+            HIPCHK(hipEventRecord(end, st));
+            if (ctmk::gemm_split_plan((int)M, (int)N, (int)K, (int)nb, gws_cap) > 1) kstat[4].launches += 1;
+            kstat[4].pending.push_back({mid, end});
+        }
     }
 
     // GEMM precision for the lifetime of the guard
@@ -1428,22 +1442,25 @@ ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes
     return CTM_OK;
 }
 
-ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops)
+ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops,
+                            double* bytes)
 {
-    if (!c || which < 0 || which > 3) return CTM_EINVAL;
+    if (!c || which < 0 || which > 4) return CTM_EINVAL;
     if (!(c->cfg.flags & CTM_FLAG_PROFILE)) { c->err = "context not built with CTM_FLAG_PROFILE"; return CTM_ESTATE; }
     return guarded(c, [&] {
         long long l = 0;
-        double t = 0.0, fl = 0.0;
+        double t = 0.0, fl = 0.0, by = 0.0;
         for (auto& x : c->w) {
             x.prof_collect();
             l += x.kstat[which].launches;
             t += x.kstat[which].ms;
             fl += x.kstat[which].flops;
+            by += x.kstat[which].bytes;
         }
         if (launches) *launches = l;
         if (ms) *ms = t;
         if (flops) *flops = fl;
+        if (bytes) *bytes = by;
     });
 }
 

@@ -39,17 +39,20 @@ struct CholBatch {
     int n;
 };
 
-// ws (may be NULL): workspace of ws_cap doubles for split-K partial products
+// ws (may be NULL): workspace of ws_cap doubles for split-K partial products;
+// mid (may be NULL): event recorded between the product and the split-K
+// reduction (profiling)
 void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
               const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
               double beta, double* C, int64_t ldc, int64_t sC, int batch,
-              double* ws = nullptr, int64_t ws_cap = 0);
+              double* ws = nullptr, int64_t ws_cap = 0, hipEvent_t mid = nullptr);
 int gemm_split_plan(int M, int N, int K, int batch, int64_t ws_cap);
 // the same product with FP32 (prec 1) or BF16 (prec 2) operands and FP32
 // accumulation; operands and result FP64 in memory
 void gemm_lp(hipStream_t s, int prec, bool ta, bool tb, int M, int N, int K, double alpha,
              const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
-             double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap);
+             double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap,
+             hipEvent_t mid = nullptr);
 void permute(hipStream_t s, const double* in, double* out, const PermDesc& pd, int64_t n);
 void dot(hipStream_t s, const double* x, const double* y, int64_t n, double* out, double* part, int mode);
 void scale_inv(hipStream_t s, double* x, int64_t n, const double* dev_scalar);

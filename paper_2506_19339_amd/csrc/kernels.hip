@@ -162,7 +162,8 @@ int gemm_split_plan(int M, int N, int K, int batch, int64_t ws_cap)
 
 void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
               const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
-              double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap)
+              double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap,
+              hipEvent_t mid)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return;
     int ksplit = (beta == 0.0 && ws) ? gemm_split_plan(M, N, K, batch, ws_cap) : 1;
@@ -182,6 +183,7 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
         hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
     else
         hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, block, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ksplit, kchunk, P);
+    if (mid) (void)hipEventRecord(mid, s);
     if (ksplit > 1) {
         const int64_t total = (int64_t)batch * M * N;
         const int g = (int)std::min<int64_t>((total + 255) / 256, 4096);
@@ -329,7 +331,8 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(
 
 void gemm_lp(hipStream_t s, int prec, bool ta, bool tb, int M, int N, int K, double alpha,
              const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
-             double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap)
+             double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap,
+             hipEvent_t mid)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return;
     int ksplit = (beta == 0.0 && ws) ? gemm_split_plan(M, N, K, batch, ws_cap) : 1;
@@ -355,6 +358,7 @@ void gemm_lp(hipStream_t s, int prec, bool ta, bool tb, int M, int N, int K, dou
         else CTM_LP_LAUNCH(true, true, 2);
     }
 #undef CTM_LP_LAUNCH
+    if (mid) (void)hipEventRecord(mid, s);
     if (ksplit > 1) {
         const int64_t total = (int64_t)batch * M * N;
         const int g = (int)std::min<int64_t>((total + 255) / 256, 4096);

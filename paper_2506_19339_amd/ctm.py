@@ -63,7 +63,7 @@ def load_library(path=None):
     lib.ctm_corner_spectrum.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.ctm_reset_tensor.argtypes = [vp, ctypes.c_double, vp]
     lib.ctm_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong)]
-    lib.ctm_kernel_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), dp, dp]
+    lib.ctm_kernel_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), dp, dp, dp]
     lib.ctm_kernel_stats.restype = ctypes.c_int
     lib.ctm_destroy.argtypes = [vp]
     lib.ctm_destroy.restype = None
@@ -171,12 +171,16 @@ class SplitCTM:
         self.beta = float(beta)
 
     def kernel_stats(self, which):
-        """(launches, total ms, algorithmic flops) of kernel class which (0 GEMM, 1 Jacobi)."""
+        """(launches, total ms, algorithmic flops, algorithmic bytes) of kernel
+        class which (0 FP64 GEMM, 1 Jacobi, 2 Cholesky QR, 3 FP32/BF16 GEMM,
+        4 split-K reduction) of a context built with profile=True."""
         n = ctypes.c_longlong(0)
         ms = ctypes.c_double(0.0)
         fl = ctypes.c_double(0.0)
-        self._check(self._lib.ctm_kernel_stats(self._ctx, int(which), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
-        return n.value, ms.value, fl.value
+        by = ctypes.c_double(0.0)
+        self._check(self._lib.ctm_kernel_stats(self._ctx, int(which), ctypes.byref(n), ctypes.byref(ms),
+                                               ctypes.byref(fl), ctypes.byref(by)))
+        return n.value, ms.value, fl.value, by.value
 
     def query(self):
         it = ctypes.c_int(0)

@@ -96,6 +96,6 @@ def test_reduced_precision_context_reports_fp32_gemm_class():
     A = raw_peps(2, 0)
     with ctm.SplitCTM(0.2, A, 16, precision=ctm.CTM_FP32, profile=True) as c:
         c.iterate(5)
-        n64, _, _ = c.kernel_stats(0)
-        n32, _, fl32 = c.kernel_stats(3)
-    assert n32 > 0 and fl32 > 0
+        n64, _, _, _ = c.kernel_stats(0)
+        n32, _, fl32, by32 = c.kernel_stats(3)
+    assert n32 > 0 and fl32 > 0 and by32 > 0
