@@ -117,10 +117,18 @@ public:
 // ---------------------------------------------------------------------------
 constexpr int kMaxRank = 12;
 
+// d[] are the logical dimensions (the order the caller's labels refer to).
+// A contraction result whose requested label order differs from the GEMM's
+// natural output order is kept in the natural order (lazy): storage axis s
+// holds logical axis sp[s].  The next contraction folds that order into its
+// own operand permutation, so the two permutes become one; view(), mm() and
+// raw-pointer consumers materialise first.
 struct Tn {
     double* p = nullptr;
     int r = 0;
     int64_t d[kMaxRank] = {0};
+    bool lazy = false;
+    int8_t sp[kMaxRank] = {0};
     int64_t n() const
     {
         int64_t s = 1;
@@ -381,7 +389,35 @@ struct Worker {
         REQUIRE(ar != std::string::npos, spec);
         const std::string li = s.substr(0, ar), lo = s.substr(ar + 2);
         REQUIRE((int)li.size() == A.r && lo.size() == li.size(), spec);
-        return permute_labels(A, li, lo);
+        std::string sl;
+        const Tn As = storage(A, li, sl);
+        return permute_labels(As, sl, lo);
+    }
+
+    // the stored array of A with its dims in storage order, and the caller's
+    // labels li rearranged to that order
+    static Tn storage(const Tn& A, const std::string& li, std::string& sl)
+    {
+        Tn S = A;
+        S.lazy = false;
+        sl = li;
+        if (!A.lazy) return S;
+        for (int k = 0; k < A.r; ++k) {
+            S.d[k] = A.d[A.sp[k]];
+            sl[k] = li[A.sp[k]];
+        }
+        return S;
+    }
+
+    // A in its logical order (a permute if A is lazy)
+    Tn mat(const Tn& A)
+    {
+        if (!A.lazy) return A;
+        std::string li;
+        for (int k = 0; k < A.r; ++k) li += (char)('a' + k);
+        std::string sl;
+        const Tn As = storage(A, li, sl);
+        return permute_labels(As, sl, li);
     }
 
     Tn permute_labels(const Tn& A, const std::string& li, const std::string& lo)
@@ -408,8 +444,9 @@ struct Worker {
         return out;
     }
 
-    static Tn view(const Tn& A, std::initializer_list<int64_t> dims)
+    Tn view(const Tn& A0, std::initializer_list<int64_t> dims)
     {
+        const Tn A = mat(A0);
         Tn t;
         t.p = A.p;
         for (int64_t v : dims) t.d[t.r++] = v;
@@ -419,13 +456,15 @@ struct Worker {
 
     // ctr("ab,bc->ac", A, B): labelled pairwise contraction.  Labels shared by
     // A, B and the output are batch labels; shared by A and B only are summed.
-    Tn ctr(const char* spec, const Tn& A, const Tn& B)
+    Tn ctr(const char* spec, const Tn& A0, const Tn& B0)
     {
         std::string s(spec);
         const size_t cm = s.find(','), ar = s.find("->");
         REQUIRE(cm != std::string::npos && ar != std::string::npos, spec);
-        const std::string la = s.substr(0, cm), lb = s.substr(cm + 1, ar - cm - 1), lo = s.substr(ar + 2);
-        REQUIRE((int)la.size() == A.r && (int)lb.size() == B.r, spec);
+        const std::string la0 = s.substr(0, cm), lb0 = s.substr(cm + 1, ar - cm - 1), lo = s.substr(ar + 2);
+        REQUIRE((int)la0.size() == A0.r && (int)lb0.size() == B0.r, spec);
+        std::string la, lb;
+        const Tn A = storage(A0, la0, la), B = storage(B0, lb0, lb);
         int64_t dim[128];
         for (int i = 0; i < 128; ++i) dim[i] = -1;
         for (int i = 0; i < A.r; ++i) dim[(int)la[i]] = A.d[i];
@@ -490,13 +529,19 @@ struct Worker {
                  C.p, N, M * N, nb);
         }
         if (lo == nat) return C;
-        return permute_labels(C, nat, lo);
+        // keep the natural order; record where each logical axis is stored
+        Tn L = C;
+        L.lazy = true;
+        for (int i = 0; i < orank; ++i) L.d[i] = dim[(int)lo[i]];
+        for (int k = 0; k < orank; ++k) L.sp[k] = (int8_t)lo.find(nat[k]);
+        return L;
     }
 
     // ---------------- dense linear algebra on row-major matrices
     // C[M][N] = op(A) op(B)
-    Tn mm(const Tn& A, bool ta, const Tn& B, bool tb)
+    Tn mm(const Tn& A0, bool ta, const Tn& B0, bool tb)
     {
+        const Tn A = mat(A0), B = mat(B0);
         const int64_t M = ta ? A.d[1] : A.d[0], K = ta ? A.d[0] : A.d[1];
         const int64_t K2 = tb ? B.d[1] : B.d[0], N = tb ? B.d[0] : B.d[1];
         REQUIRE(A.r == 2 && B.r == 2 && K == K2, "mm shapes");
@@ -889,9 +934,12 @@ void Worker::step(Net& N, int64_t chi)
     Tn Tb_n = ctr("naobmt,kbaot->nmk", X, PbkT);
     // ---- corners: second-stage projectors on the stage-1 renormalised corners
     Tn W1 = ctr("cdfqre,Xqre->cdfX", C1p, P4T);
-    Tn C1_n = ctr("cdfX,Ycdf->XY", W1, P4T);
+    Tn C1_n = mat(ctr("cdfX,Ycdf->XY", W1, P4T));
     Tn W4 = ctr("cwhXyi,cwhx->xXyi", C4p, P4B);
-    Tn C4_n = ctr("xXyi,Xyiz->xz", W4, P4B);
+    Tn C4_n = mat(ctr("xXyi,Xyiz->xz", W4, P4B));
+    Tk_n = mat(Tk_n);
+    Ti_n = mat(Ti_n);
+    Tb_n = mat(Tb_n);
     ctmk::symmetrize(st, C1_n.p, (int)k4);
     ctmk::symmetrize(st, C4_n.p, (int)k4);
     normalize(C1_n);
@@ -903,7 +951,7 @@ void Worker::step(Net& N, int64_t chi)
     // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form)
     Prec spec64(*this, CTM_FP64);
     Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
-    Tn R = ctr("ab,bc->ac", R1, R1);
+    Tn R = mat(ctr("ab,bc->ac", R1, R1));
     ctmk::trace(st, R.p, (int)k4, N.sc + 7);
     std::vector<JReq> sp{JReq{R.p, k4, k4, false, {}, {}, {}}};
     jacobi_batch(sp);
@@ -970,7 +1018,7 @@ void Worker::values(Net& N, bool with_env)
     if (with_env) {
         Tn G = ctr("jqtnbk,jwv->qtnbwvk", upib, Bt);
         G = ctr("qtnbwvk,ksz->qtnbwvsz", G, Rb);
-        Tn Env = ctr("qtnbwvsz,vntez->qwbse", G, BR);   // [q, Bl, Bu, Br, Bd]
+        Tn Env = mat(ctr("qtnbwvsz,vntez->qwbse", G, BR));   // [q, Bl, Bu, Br, Bd]
         ctmk::copy(st, Env.p, N.E, Env.n());
         ctmk::dot(st, Env.p, this->A, Env.n(), N.sc + 6, part, 0);
     }

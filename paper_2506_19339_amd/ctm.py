@@ -50,6 +50,14 @@ def load_library(path=None):
     p = path or library_path()
     if not os.path.exists(p):
         raise OSError("HIP library %s not found: build it with __graft_entry__.build()" % p)
+    # One HIP runtime per process: when PyTorch is installed its bundled
+    # runtime (same soname) must be the one the library binds to, so torch is
+    # imported first; loading the library first would pull in a second
+    # runtime under torch.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     dp = ctypes.POINTER(ctypes.c_double)
     vp = ctypes.c_void_p
