@@ -384,6 +384,29 @@ __global__ void permute_kernel(const double* __restrict__ in, double* __restrict
     }
 }
 
+// 32-bit form (fewer than 2^31 elements): the mixed-radix digits of the output
+// index come from division by invariant integers, q = (umulhi(x, mul) + x) >> s
+// with s = ceil(log2 d) and mul = floor(2^32 (2^s - d) / d) + 1, exact for
+// x < 2^31.
+struct PermDesc32 {
+    int rank;
+    uint32_t od[12], is[12], mul[12], shr[12];
+};
+
+__global__ void permute32_kernel(const double* __restrict__ in, double* __restrict__ out, uint32_t n,
+                                 PermDesc32 pd)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        uint32_t rem = i, off = 0;
+        for (int k = pd.rank - 1; k >= 0; --k) {
+            const uint32_t q = (__umulhi(rem, pd.mul[k]) + rem) >> pd.shr[k];
+            off += (rem - q * pd.od[k]) * pd.is[k];
+            rem = q;
+        }
+        out[i] = in[off];
+    }
+}
+
 static int grid_for(int64_t n, int block = 256, int cap = 8192)
 {
     int64_t g = (n + block - 1) / block;
@@ -395,7 +418,27 @@ static int grid_for(int64_t n, int block = 256, int cap = 8192)
 void permute(hipStream_t s, const double* in, double* out, const PermDesc& pd, int64_t n)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n, pd);
+    const int64_t lim = (int64_t)1 << 31;
+    bool small = n < lim;
+    int64_t span = 1;   // largest input offset + 1
+    for (int k = 0; k < pd.rank; ++k) span += (pd.od[k] - 1) * pd.is[k];
+    small = small && span < lim;
+    if (small) {
+        PermDesc32 p32{};
+        p32.rank = pd.rank;
+        for (int k = 0; k < pd.rank; ++k) {
+            const uint64_t d = (uint64_t)pd.od[k];
+            uint32_t sh = 0;
+            while (((uint64_t)1 << sh) < d) ++sh;
+            p32.od[k] = (uint32_t)d;
+            p32.is[k] = (uint32_t)pd.is[k];
+            p32.shr[k] = sh;
+            p32.mul[k] = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << sh) - d)) / d + 1);
+        }
+        hipLaunchKernelGGL(permute32_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, (uint32_t)n, p32);
+    } else {
+        hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n, pd);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -57,6 +57,31 @@ int ctm_selftest_gemm_lp(int prec, int ta, int tb, int M, int N, int K, int batc
     return rc;
 }
 
+// out = transpose(in, axes): in has dims[0..rank-1] (row-major), out axis k is
+// input axis axes[k]
+int ctm_selftest_permute(int rank, const long long* dims, const int* axes, const double* in, double* out)
+{
+    int64_t n = 1, stride[12];
+    for (int k = rank - 1; k >= 0; --k) {
+        stride[k] = n;
+        n *= dims[k];
+    }
+    ctmk::PermDesc pd{};
+    pd.rank = rank;
+    for (int k = 0; k < rank; ++k) {
+        pd.od[k] = dims[axes[k]];
+        pd.is[k] = stride[axes[k]];
+    }
+    double *di = dev_copy(in, (size_t)n), *dout = dev_copy<double>(nullptr, (size_t)n);
+    if (!di || !dout) return 1;
+    ctmk::permute(nullptr, di, dout, pd, n);
+    int rc = hipMemcpy(out, dout, (size_t)n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
+    rc |= hipDeviceSynchronize() != hipSuccess;
+    (void)hipFree(di);
+    (void)hipFree(dout);
+    return rc;
+}
+
 // number of K slices gemm_f64 uses for this shape and workspace
 int ctm_selftest_gemm_splits(int M, int N, int K, int batch, long long ws_cap)
 {

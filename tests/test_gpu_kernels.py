@@ -21,6 +21,8 @@ def lib():
     dp = ctypes.POINTER(ctypes.c_double)
     L.ctm_selftest_gemm.argtypes = [ctypes.c_int] * 6 + [dp, dp, dp, ctypes.c_longlong]
     L.ctm_selftest_gemm_lp.argtypes = [ctypes.c_int] * 7 + [dp, dp, dp, ctypes.c_longlong]
+    L.ctm_selftest_permute.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                       ctypes.POINTER(ctypes.c_int), dp, dp]
     L.ctm_selftest_gemm_splits.argtypes = [ctypes.c_int] * 4 + [ctypes.c_longlong]
     L.ctm_selftest_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
     L.ctm_selftest_cholqr.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
@@ -56,6 +58,20 @@ def test_gemm_split_k_matches_numpy(lib, ta, tb, M, N, K, batch):
     cap = 1 << 22
     assert lib.ctm_selftest_gemm_splits(M, N, K, batch, cap) > 1
     _gemm_case(lib, ta, tb, M, N, K, batch, cap)
+
+
+@pytest.mark.parametrize("dims,axes", [((7,), (0,)), ((3, 5), (1, 0)), ((2, 3, 4, 5), (3, 1, 0, 2)),
+                                       ((5, 2, 100, 2, 5, 2), (4, 0, 5, 2, 1, 3)),
+                                       ((100, 5, 5, 2, 2, 5, 5, 2, 2), (0, 2, 4, 6, 8, 1, 3, 5, 7)),
+                                       ((1, 1, 3, 1), (3, 2, 1, 0))])
+def test_permute_matches_numpy(lib, dims, axes):
+    rng = np.random.default_rng(len(dims))
+    x = rng.standard_normal(dims)
+    out = np.zeros(int(np.prod(dims)))
+    d = (ctypes.c_longlong * len(dims))(*dims)
+    a = (ctypes.c_int * len(axes))(*axes)
+    assert lib.ctm_selftest_permute(len(dims), d, a, _p(np.ascontiguousarray(x)), _p(out)) == 0
+    assert np.array_equal(out.reshape([dims[k] for k in axes]), np.transpose(x, axes))
 
 
 def _round_bf16(x):
