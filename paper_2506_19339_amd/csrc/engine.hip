@@ -178,6 +178,7 @@ struct KStat {
 constexpr int kJacobiExact = 64;    // exact Jacobi SVD when min(m, n) <= this
 constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resident)
 constexpr int kOversample = 16;
+constexpr int kWarmPowerIters = 4;  // power steps when every subspace starts from last move's
 constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resident Jacobi)
 // relative pseudo-inverse cutoff of S^1/2: singular values of rho_B rho_T below
 // 1e-8 of the largest are dropped.  The subspace factorisation squares the
@@ -219,6 +220,8 @@ struct Worker {
     uint64_t svd_calls = 0;
     int64_t exact_min = kJacobiExact, exact_area = kJacobiExactArea;
     int64_t trace_perm = 0;          // testing aid: log permutes of at least this many elements
+    bool trace_gemm = false;         // testing aid: log GEMM shapes
+    bool warm_starts = true;         // subspace iterations start from last move's vectors
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
     double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
     int cur = CTM_FP64;              // precision of the GEMMs issued now
@@ -326,6 +329,9 @@ struct Worker {
               int64_t sA, const double* B, int64_t ldb, int64_t sB, double* C, int64_t ldc,
               int64_t sC, int64_t nb)
     {
+        if (trace_gemm)
+            std::fprintf(stderr, "gemm %lld %lld %lld %lld %d %d %d\n", (long long)M, (long long)N, (long long)K,
+                         (long long)nb, (int)ta, (int)tb, cur);
         hipEvent_t e = prof_begin();
         hipEvent_t mid = profiling ? ev_get() : nullptr;
         if (cur == CTM_FP64)
@@ -633,8 +639,20 @@ struct Worker {
     struct SvdReq {
         Tn M;
         int64_t kk;
+        int slot = -1;               // projector slot (warm start), -1: none
         Tn UT, S, VT;
     };
+
+    // right singular vectors kept by each projector slot in the last move, the
+    // start of the next subspace iteration of that slot (with a fixed sign
+    // convention the bond gauge, and with it rho_B rho_T, settles as the
+    // environment converges)
+    struct Warm {
+        double* V = nullptr;
+        int64_t cap = 0, kk = 0, n = 0;
+        bool valid = false;
+    };
+    Warm warm[6];
     void svd_batch(std::vector<SvdReq>& rq)
     {
         Prec fp64(*this, CTM_FP64);   // factorisations stay FP64 in every precision form
@@ -682,6 +700,7 @@ struct Worker {
         // a random one.
         const size_t nr = rnd.size();
         std::vector<Tn> Pt(nr), Qt(nr);
+        bool all_warm = true;
         for (size_t j = 0; j < nr; ++j) {
             const SvdReq& r = rq[rnd[j]];
             const int64_t m = r.M.d[0], n = r.M.d[1], mn = std::min(m, n);
@@ -689,11 +708,16 @@ struct Worker {
                 std::max<int64_t>(std::min<int64_t>(2 * r.kk, kCoreMax), r.kk + kOversample), mn);
             Pt[j] = tmp({k, n});
             ctmk::randn(st, Pt[j].p, k * n, 0x5eedull + 7919ull * (++svd_calls));
+            const Warm* w = (warm_starts && r.slot >= 0) ? &warm[r.slot] : nullptr;
+            if (w && w->valid && w->n == n && w->kk <= k)
+                ctmk::copy(st, w->V, Pt[j].p, w->kk * n);   // last move's kept vectors first
+            else
+                all_warm = false;
         }
         // inside the power steps one Cholesky-QR pass keeps the basis well
         // conditioned; the bases that enter the Rayleigh-Ritz core (last P, Q)
         // get the second pass that makes them orthonormal
-        const int q = cfg.power_iters > 0 ? cfg.power_iters : 10;
+        const int q = cfg.power_iters > 0 ? cfg.power_iters : (all_warm ? kWarmPowerIters : 10);
         cholqr_pass(Pt);
         for (int it = 0; it < q; ++it) {
             for (size_t j = 0; j < nr; ++j) Qt[j] = mm(Pt[j], false, rq[rnd[j]].M, true);   // (M P)^T
@@ -720,6 +744,18 @@ struct Worker {
             Tn Ujt = make_tn(core[j].U.p, {k, k});   // rows = right vectors of Bs
             Tn UTf = mm(Vjt, false, Qt[j], false);   // (Q Us)^T
             Tn VTf = mm(Ujt, false, Pt[j], false);   // (P Vs)^T
+            ctmk::sign_fix(st, UTf.p, VTf.p, (int)r.kk, (int)m, (int)n);
+            if (warm_starts && r.slot >= 0) {
+                Warm& w = warm[r.slot];
+                if (w.cap < r.kk * n) {
+                    w.V = keep(r.kk * n);
+                    w.cap = r.kk * n;
+                }
+                ctmk::copy(st, VTf.p, w.V, r.kk * n);
+                w.kk = r.kk;
+                w.n = n;
+                w.valid = true;
+            }
             r.UT = make_tn(UTf.p, {r.kk, m});
             r.VT = make_tn(VTf.p, {r.kk, n});
             r.S = make_tn(core[j].S.p, {r.kk});
@@ -729,7 +765,7 @@ struct Worker {
     // projector pairs from (rhoT (t x rT), rhoB (rB x t)) for every entry of
     // the list; the factorisations of all entries share their launches and one
     // read-back of the kept ranks.
-    std::vector<Projector> projectors(const std::vector<std::pair<Tn, Tn>>& prs, int64_t chi)
+    std::vector<Projector> projectors(const std::vector<std::pair<Tn, Tn>>& prs, int64_t chi, int slot0)
     {
         REQUIRE(prs.size() <= (size_t)kMaxBatch, "too many projectors in one batch");
         std::vector<Projector> out(prs.size());
@@ -755,6 +791,7 @@ struct Worker {
                 r.M = mm(rB, false, rT, false);      // remB x remT
             }
             r.kk = std::min<int64_t>(chi, std::min(remB, remT));
+            r.slot = slot0 + (int)i;
             rq.push_back(r);
             of.push_back(i);
         }
@@ -848,7 +885,7 @@ void Worker::step(Net& N, int64_t chi)
         {{view(rT1, {xbk * D, D * d * xbk}), view(rB1, {D * d * xbk, xbk * D})},
          {view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D})},
          {view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P})}},
-        chi);
+        chi, 0);
     const Projector &P1 = S1[0], &P2 = S1[1], &P3 = S1[2];
     const int64_t c1 = P1.k, c2 = P2.k, c3 = P3.k;
     Tn P1T = view(P1.PT, {c1, xbk, D}), P1B = view(P1.PB, {xbk, D, c1});
@@ -907,7 +944,7 @@ void Worker::step(Net& N, int64_t chi)
         {{view(C1p, {n4, n4}), view(rB4, {n4, n4})},
          {view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P})},
          {view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d})}},
-        chi);
+        chi, 3);
     const Projector &P4 = S2[0], &P5 = S2[1], &P6 = S2[2];
     const int64_t k4 = P4.k, k5 = P5.k, k6 = P6.k;
     Tn P4T = view(P4.PT, {k4, c1, D, d}), P4B = view(P4.PB, {c1, D, d, k4});
@@ -1350,9 +1387,16 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
             }
             if (const char* e = std::getenv("CTM_TRACE_PERMUTE")) x.trace_perm = std::atoll(e);   // testing aid
             if (const char* e = std::getenv("CTM_LP_CUTOFF")) x.lp_cut = std::atof(e);            // testing aid
+            if (std::getenv("CTM_TRACE_GEMM")) x.trace_gemm = true;                                // testing aid
+            if (std::getenv("CTM_NO_WARM_SVD")) x.warm_starts = false;                             // testing aid
         }
         HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         for (auto& e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        // the norm network's subspaces start cold every move: started from the
+        // last move's vectors with the short power iteration, its unconverged
+        // moves drift from those of the exact truncation by ~1e-5 in ln kappa
+        // (the triple layer's stay within 1e-10)
+        c->w[1].warm_starts = false;
         init_net(c, c->net[0], 2);
         init_net(c, c->net[1], 1);
         c->fork();

@@ -78,6 +78,9 @@ void trace(hipStream_t s, const double* X, int n, double* out);
 void finite_check(hipStream_t s, const double* x, int64_t n, int* flag);
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps);
 void cholqr(hipStream_t s, const CholBatch& jobs, double shift);
+// negate row i of UT (rows x m) and VT (rows x n) when UT's largest-magnitude
+// entry in that row is negative
+void sign_fix(hipStream_t s, double* UT, double* VT, int rows, int m, int n);
 
 constexpr int kRedBlocks = 256;  // partial-sum slots needed by dot()
 

@@ -442,6 +442,48 @@ void permute(hipStream_t s, const double* in, double* out, const PermDesc& pd, i
 }
 
 // ---------------------------------------------------------------------------
+// sign convention of singular vectors: row i of UT (kk x m) and VT (kk x n)
+// are negated when the entry of UT's row with the largest magnitude (first
+// one on ties) is negative.  One block per row.
+// ---------------------------------------------------------------------------
+__global__ void sign_fix_kernel(double* __restrict__ UT, double* __restrict__ VT, int m, int n)
+{
+    __shared__ double bv[256];
+    __shared__ int bi[256];
+    const int row = blockIdx.x, tid = threadIdx.x;
+    double* u = UT + (int64_t)row * m;
+    double best = -1.0;
+    int idx = m;
+    for (int j = tid; j < m; j += blockDim.x) {
+        const double a = fabs(u[j]);
+        if (a > best) { best = a; idx = j; }
+    }
+    bv[tid] = best;
+    bi[tid] = idx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            const double b2 = bv[tid + o];
+            const int i2 = bi[tid + o];
+            if (b2 > bv[tid] || (b2 == bv[tid] && i2 < bi[tid])) { bv[tid] = b2; bi[tid] = i2; }
+        }
+        __syncthreads();
+    }
+    const int jm = bi[0];
+    if (jm < m && u[jm] < 0.0) {
+        double* v = VT + (int64_t)row * n;
+        for (int j = tid; j < m; j += blockDim.x) u[j] = -u[j];
+        for (int j = tid; j < n; j += blockDim.x) v[j] = -v[j];
+    }
+}
+
+void sign_fix(hipStream_t s, double* UT, double* VT, int rows, int m, int n)
+{
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(sign_fix_kernel, dim3(rows), dim3(256), 0, s, UT, VT, m, n);
+}
+
+// ---------------------------------------------------------------------------
 // reductions (deterministic: fixed grid, fixed tree)
 // ---------------------------------------------------------------------------
 constexpr int RED_BLOCKS = 256;
