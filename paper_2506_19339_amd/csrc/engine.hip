@@ -163,6 +163,8 @@ struct Net {
     double* sc = nullptr;            // scalars: n1 n2h n2v n0 | lk flag | tr
     double* E = nullptr;             // bra environment, 2 D^4
     double* sv = nullptr;            // spectrum buffer
+    double* spG = nullptr;           // right singular vectors of the last spectrum matrix (rows)
+    int64_t spG_n = 0;               // their size, 0: none yet
 };
 
 // per-kernel-class launch statistics (CTM_FLAG_PROFILE): HIP events on the
@@ -179,6 +181,7 @@ constexpr int kJacobiExact = 64;    // exact Jacobi SVD when min(m, n) <= this
 constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resident)
 constexpr int kOversample = 16;
 constexpr int kWarmPowerIters = 4;  // power steps when every subspace starts from last move's
+constexpr double kWarmGate = 1e-5;  // spectrum change per move below which the last bases are reused
 constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resident Jacobi)
 // relative pseudo-inverse cutoff of S^1/2: singular values of rho_B rho_T below
 // 1e-8 of the largest are dropped.  The subspace factorisation squares the
@@ -221,7 +224,8 @@ struct Worker {
     int64_t exact_min = kJacobiExact, exact_area = kJacobiExactArea;
     int64_t trace_perm = 0;          // testing aid: log permutes of at least this many elements
     bool trace_gemm = false;         // testing aid: log GEMM shapes
-    bool warm_starts = true;         // subspace iterations start from last move's vectors
+    bool warm_starts = true;         // keep each slot's Ritz basis for the next move
+    double last_delta = 1.0;         // spectrum change of this network's last move (host copy)
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
     double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
     int cur = CTM_FP64;              // precision of the GEMMs issued now
@@ -695,9 +699,10 @@ struct Worker {
         // oversampling: near the cut the spectra of these environments are
         // flat (sigma_{1.28 chi} / sigma_chi ~ 0.3-0.5), so the subspace extends
         // to min(2 kk, 128) vectors (at least kk + 16) and ten power steps
-        // resolve the kept singular values to ~1e-11.  The bond gauge changes
-        // every iteration, so the previous subspace is no better a start than
-        // a random one.
+        // resolve the kept singular values to ~1e-11.  With the sign
+        // convention of sign_fix the bond gauge settles as the environment
+        // converges, and the last move's Ritz basis of a slot is then a far
+        // better start than random normals (fewer power steps).
         const size_t nr = rnd.size();
         std::vector<Tn> Pt(nr), Qt(nr);
         bool all_warm = true;
@@ -708,9 +713,13 @@ struct Worker {
                 std::max<int64_t>(std::min<int64_t>(2 * r.kk, kCoreMax), r.kk + kOversample), mn);
             Pt[j] = tmp({k, n});
             ctmk::randn(st, Pt[j].p, k * n, 0x5eedull + 7919ull * (++svd_calls));
-            const Warm* w = (warm_starts && r.slot >= 0) ? &warm[r.slot] : nullptr;
+            // a slot starts from its last basis once the network's spectrum
+            // moves by less than kWarmGate per move; earlier, while the
+            // environment still changes a lot, it starts from fresh normals
+            const bool use = warm_starts && r.slot >= 0 && last_delta < kWarmGate;
+            const Warm* w = use ? &warm[r.slot] : nullptr;
             if (w && w->valid && w->n == n && w->kk <= k)
-                ctmk::copy(st, w->V, Pt[j].p, w->kk * n);   // last move's kept vectors first
+                ctmk::copy(st, w->V, Pt[j].p, w->kk * n);   // last move's Ritz vectors first
             else
                 all_warm = false;
         }
@@ -746,13 +755,15 @@ struct Worker {
             Tn VTf = mm(Ujt, false, Pt[j], false);   // (P Vs)^T
             ctmk::sign_fix(st, UTf.p, VTf.p, (int)r.kk, (int)m, (int)n);
             if (warm_starts && r.slot >= 0) {
+                // the whole Ritz basis (kept and oversampling vectors) starts
+                // the next move's iteration of this slot
                 Warm& w = warm[r.slot];
-                if (w.cap < r.kk * n) {
-                    w.V = keep(r.kk * n);
-                    w.cap = r.kk * n;
+                if (w.cap < k * n) {
+                    w.V = keep(k * n);
+                    w.cap = k * n;
                 }
-                ctmk::copy(st, VTf.p, w.V, r.kk * n);
-                w.kk = r.kk;
+                ctmk::copy(st, VTf.p, w.V, k * n);
+                w.kk = k;
                 w.n = n;
                 w.valid = true;
             }
@@ -985,14 +996,25 @@ void Worker::step(Net& N, int64_t chi)
     normalize(Ti_n);
     normalize(Tb_n);
 
-    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form)
+    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form).
+    // The rows of the matrix are first combined by the right singular vectors
+    // of the last move's matrix (an orthogonal factor, so the singular values
+    // are unchanged).  In the sign-fixed bond gauge of a settling environment
+    // the combined rows are already close to orthogonal and the one-sided
+    // Jacobi needs few sweeps; the accumulated factor is kept for the next move.
     Prec spec64(*this, CTM_FP64);
     Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
     Tn R = mat(ctr("ab,bc->ac", R1, R1));
     ctmk::trace(st, R.p, (int)k4, N.sc + 7);
-    std::vector<JReq> sp{JReq{R.p, k4, k4, false, {}, {}, {}}};
+    const bool turned = N.spG_n == k4;
+    const Tn G0 = make_tn(N.spG, {k4, k4});
+    const Tn Y = turned ? mm(G0, false, R, false) : R;
+    std::vector<JReq> sp{JReq{Y.p, k4, k4, true, {}, {}, {}}};
     jacobi_batch(sp);
     ctmk::spectrum_delta(st, sp[0].S.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
+    const Tn G1 = turned ? mm(sp[0].V, false, G0, false) : sp[0].V;
+    ctmk::copy(st, G1.p, N.spG, k4 * k4);
+    N.spG_n = k4;
 
     // ---- store
     N.xbk = k4;
@@ -1176,12 +1198,15 @@ static void init_net(ctm_ctx* c, Net& N, int d)
     N.sc = c->keep(16);
     N.E = c->keep(2 * D * D * D * D);
     N.sv = c->keep(x);
+    N.spG = c->keep(x * x);
 }
 
 static void reset_env(Worker& W, Net& N, int D)
 {
     const int64_t d = N.d;
     N.xbk = N.xki = N.xib = 1;
+    N.spG_n = 0;
+    W.last_delta = 1.0;
     ctmk::fill(W.st, N.C1, 1, 1.0);
     ctmk::fill(W.st, N.C4, 1, 1.0);
     ctmk::fill(W.st, N.Tk, D, 1.0 / std::sqrt((double)D));
@@ -1286,12 +1311,15 @@ static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done,
                 const int prec = c->lp_done ? CTM_FP64 : c->cfg.precision;   // of the triple layer
                 ++c->iters;
                 ++done[i];
-                if (until || done[i] == budget[i]) {
+                {
+                    // every move: the spectrum changes decide convergence and
+                    // whether the next move's subspace iterations start warm
                     double h[2];
                     for (int wi = 0; wi < 2; ++wi)
                         HIPCHK(hipMemcpyAsync(&h[wi], c->net[wi].delta, sizeof(double), hipMemcpyDeviceToHost,
                                               c->w[wi].st));
                     sync_workers(c);
+                    for (int wi = 0; wi < 2; ++wi) c->w[wi].last_delta = std::isfinite(h[wi]) ? h[wi] : 1.0;
                     dl[i] = std::max(h[0], h[1]);
                     if (!std::isfinite(dl[i])) throw CtmError(CTM_ENUMERIC, "non-finite spectrum");
                     if (until && c->iters > 1) {
@@ -1392,11 +1420,6 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
         }
         HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         for (auto& e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        // the norm network's subspaces start cold every move: started from the
-        // last move's vectors with the short power iteration, its unconverged
-        // moves drift from those of the exact truncation by ~1e-5 in ln kappa
-        // (the triple layer's stay within 1e-10)
-        c->w[1].warm_starts = false;
         init_net(c, c->net[0], 2);
         init_net(c, c->net[1], 1);
         c->fork();
@@ -1517,6 +1540,7 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A)
         c->join();
         c->lp_done = false;
         c->base_iters = c->iters;
+        for (auto& x : c->w) x.last_delta = 1.0;   // the first move on the new tensor starts cold
     });
 }
 
