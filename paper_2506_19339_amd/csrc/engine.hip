@@ -224,6 +224,8 @@ struct Worker {
     int64_t exact_min = kJacobiExact, exact_area = kJacobiExactArea;
     int64_t trace_perm = 0;          // testing aid: log permutes of at least this many elements
     bool trace_gemm = false;         // testing aid: log GEMM shapes
+    bool no_group = false;           // testing aid: one launch per product in mm_group
+    bool no_turn = false;            // testing aid: spectrum Jacobi on the plain matrix
     bool warm_starts = true;         // keep each slot's Ritz basis for the next move
     double last_delta = 1.0;         // spectrum change of this network's last move (host copy)
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
@@ -344,18 +346,23 @@ struct Worker {
         else
             ctmk::gemm_lp(st, cur, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC,
                           (int)nb, gws, gws_cap, mid);
-        if (profiling) {
-            // product kernel [e, mid], split-K reduction [mid, end]
-            const int cls = cur == CTM_FP64 ? 0 : 3;
-            kstat[cls].launches += 1;
-            kstat[cls].flops += 2.0 * (double)M * (double)N * (double)K * (double)nb;
-            kstat[cls].bytes += 8.0 * ((double)M * K + (double)K * N + (double)M * N) * (double)nb;
-            kstat[cls].pending.push_back({e, mid});
-            hipEvent_t end = ev_get();
-            HIPCHK(hipEventRecord(end, st));
-            if (ctmk::gemm_split_plan((int)M, (int)N, (int)K, (int)nb, gws_cap) > 1) kstat[4].launches += 1;
-            kstat[4].pending.push_back({mid, end});
-        }
+        if (profiling)
+            prof_gemm(e, mid, 2.0 * (double)M * (double)N * (double)K * (double)nb,
+                      8.0 * ((double)M * K + (double)K * N + (double)M * N) * (double)nb,
+                      ctmk::gemm_split_plan((int)M, (int)N, (int)K, (int)nb, gws_cap) > 1);
+    }
+    // profile mode: product kernel [e, mid], split-K reduction [mid, end]
+    void prof_gemm(hipEvent_t e, hipEvent_t mid, double flops, double bytes, bool split)
+    {
+        const int cls = cur == CTM_FP64 ? 0 : 3;
+        kstat[cls].launches += 1;
+        kstat[cls].flops += flops;
+        kstat[cls].bytes += bytes;
+        kstat[cls].pending.push_back({e, mid});
+        hipEvent_t end = ev_get();
+        HIPCHK(hipEventRecord(end, st));
+        if (split) kstat[4].launches += 1;
+        kstat[4].pending.push_back({mid, end});
     }
 
     // GEMM precision for the lifetime of the guard
@@ -560,6 +567,43 @@ struct Worker {
         return C;
     }
 
+    // C_i = op(A_i) op(B_i) for every i of the lists, the products of up to
+    // kMaxGemmGroup problems in one launch (FP64 GEMMs; in a reduced-precision
+    // phase one launch per problem)
+    std::vector<Tn> mm_group(const std::vector<Tn>& A0, bool ta, const std::vector<Tn>& B0, bool tb)
+    {
+        REQUIRE(A0.size() == B0.size(), "mm_group: list sizes");
+        std::vector<Tn> C(A0.size());
+        if (cur != CTM_FP64 || A0.size() == 1 || no_group) {
+            for (size_t i = 0; i < A0.size(); ++i) C[i] = mm(A0[i], ta, B0[i], tb);
+            return C;
+        }
+        for (size_t b0 = 0; b0 < A0.size(); b0 += ctmk::kMaxGemmGroup) {
+            const size_t b1 = std::min(A0.size(), b0 + (size_t)ctmk::kMaxGemmGroup);
+            ctmk::GemmProb pr[ctmk::kMaxGemmGroup];
+            int np = 0;
+            double fl = 0.0, by = 0.0;
+            for (size_t i = b0; i < b1; ++i) {
+                const Tn A = mat(A0[i]), B = mat(B0[i]);
+                const int64_t M = ta ? A.d[1] : A.d[0], K = ta ? A.d[0] : A.d[1];
+                const int64_t K2 = tb ? B.d[1] : B.d[0], N = tb ? B.d[0] : B.d[1];
+                REQUIRE(A.r == 2 && B.r == 2 && K == K2, "mm shapes");
+                C[i] = tmp({M, N});
+                pr[np++] = ctmk::GemmProb{A.p, B.p, C[i].p, (int)M, (int)N, (int)K, A.d[1], B.d[1], N};
+                fl += 2.0 * (double)M * (double)N * (double)K;
+                by += 8.0 * ((double)M * K + (double)K * N + (double)M * N);
+                if (trace_gemm)
+                    std::fprintf(stderr, "gemm %lld %lld %lld group %d %d\n", (long long)M, (long long)N,
+                                 (long long)K, (int)ta, (int)tb);
+            }
+            hipEvent_t e = prof_begin();
+            hipEvent_t mid = profiling ? ev_get() : nullptr;
+            ctmk::gemm_f64_group(st, ta, tb, pr, np, 1.0, gws, gws_cap, mid);
+            if (profiling) prof_gemm(e, mid, fl, by, ctmk::gemm_group_splits(pr, np, gws_cap) > 0);
+        }
+        return C;
+    }
+
     // ---------------- batched factorisations
     // One-sided Jacobi SVDs of matrices given column-major (m rows, n columns),
     // all problems of the list in one launch per group of kMaxJacobiBatch:
@@ -609,19 +653,20 @@ struct Worker {
             const size_t b1 = std::min(Ys.size(), b0 + (size_t)ctmk::kMaxJacobiBatch);
             ctmk::CholBatch cb{};
             double fl = 0.0;
+            const std::vector<Tn> Yb(Ys.begin() + b0, Ys.begin() + b1);
+            const std::vector<Tn> Gs = mm_group(Yb, false, Yb, true);   // Gram matrices
             for (size_t i = b0; i < b1; ++i) {
                 const int64_t k = Ys[i].d[0];
                 fl += 2.0 / 3.0 * (double)k * (double)k * (double)k;   // elimination: 2 sum_i i^2
-                Tn G = mm(Ys[i], false, Ys[i], true);
                 Ts[i] = tmp({k, k});
                 Tn work = tmp({2 * k});
-                cb.job[cb.n++] = ctmk::CholJob{G.p, work.p, Ts[i].p, (int)k};
+                cb.job[cb.n++] = ctmk::CholJob{Gs[i - b0].p, work.p, Ts[i].p, (int)k};
             }
             hipEvent_t e = prof_begin();
             ctmk::cholqr(st, cb, 1e-14);
             prof_end(2, e, fl);
         }
-        for (size_t i = 0; i < Ys.size(); ++i) Ys[i] = mm(Ts[i], false, Ys[i], false);
+        Ys = mm_group(Ts, false, Ys, false);
     }
 
     // rows of every Y -> orthonormal rows spanning the same space (shifted
@@ -727,32 +772,39 @@ struct Worker {
         // conditioned; the bases that enter the Rayleigh-Ritz core (last P, Q)
         // get the second pass that makes them orthonormal
         const int q = cfg.power_iters > 0 ? cfg.power_iters : (all_warm ? kWarmPowerIters : 10);
+        std::vector<Tn> Ms(nr);
+        for (size_t j = 0; j < nr; ++j) Ms[j] = rq[rnd[j]].M;
         cholqr_pass(Pt);
         for (int it = 0; it < q; ++it) {
-            for (size_t j = 0; j < nr; ++j) Qt[j] = mm(Pt[j], false, rq[rnd[j]].M, true);   // (M P)^T
+            Qt = mm_group(Pt, false, Ms, true);    // (M P)^T
             cholqr_pass(Qt);
-            for (size_t j = 0; j < nr; ++j) Pt[j] = mm(Qt[j], false, rq[rnd[j]].M, false);  // (M^T Q)^T
+            Pt = mm_group(Qt, false, Ms, false);   // (M^T Q)^T
             if (it + 1 < q) cholqr_pass(Pt);
             else orth(Pt);
         }
-        for (size_t j = 0; j < nr; ++j) Qt[j] = mm(Pt[j], false, rq[rnd[j]].M, true);
+        Qt = mm_group(Pt, false, Ms, true);
         orth(Qt);
+        const std::vector<Tn> X1 = mm_group(Qt, false, Ms, false);   // Q^T M   (k x n)
+        const std::vector<Tn> Bs = mm_group(X1, false, Pt, true);    // Q^T M P (k x k)
         std::vector<JReq> core(nr);
         for (size_t j = 0; j < nr; ++j) {
-            Tn X1 = mm(Qt[j], false, rq[rnd[j]].M, false);   // Q^T M   (k x n)
-            Tn Bs = mm(X1, false, Pt[j], true);               // Q^T M P (k x k)
-            const int64_t k = Bs.d[0];
+            const int64_t k = Bs[j].d[0];
             // Bs row-major == Bs^T col-major: Bs^T = Uj S Vj^T -> Bs = Vj S Uj^T
-            core[j] = JReq{Bs.p, k, k, true, {}, {}, {}};
+            core[j] = JReq{Bs[j].p, k, k, true, {}, {}, {}};
         }
         jacobi_batch(core);
+        std::vector<Tn> Vjt(nr), Ujt(nr);
+        for (size_t j = 0; j < nr; ++j) {
+            const int64_t k = core[j].S.d[0];
+            Vjt[j] = make_tn(core[j].V.p, {k, k});   // rows = left vectors of Bs
+            Ujt[j] = make_tn(core[j].U.p, {k, k});   // rows = right vectors of Bs
+        }
+        const std::vector<Tn> UTs = mm_group(Vjt, false, Qt, false);   // (Q Us)^T
+        const std::vector<Tn> VTs = mm_group(Ujt, false, Pt, false);   // (P Vs)^T
         for (size_t j = 0; j < nr; ++j) {
             SvdReq& r = rq[rnd[j]];
             const int64_t m = r.M.d[0], n = r.M.d[1], k = core[j].S.d[0];
-            Tn Vjt = make_tn(core[j].V.p, {k, k});   // rows = left vectors of Bs
-            Tn Ujt = make_tn(core[j].U.p, {k, k});   // rows = right vectors of Bs
-            Tn UTf = mm(Vjt, false, Qt[j], false);   // (Q Us)^T
-            Tn VTf = mm(Ujt, false, Pt[j], false);   // (P Vs)^T
+            const Tn &UTf = UTs[j], &VTf = VTs[j];
             ctmk::sign_fix(st, UTf.p, VTf.p, (int)r.kk, (int)m, (int)n);
             if (warm_starts && r.slot >= 0) {
                 // the whole Ritz basis (kept and oversampling vectors) starts
@@ -1006,7 +1058,7 @@ void Worker::step(Net& N, int64_t chi)
     Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
     Tn R = mat(ctr("ab,bc->ac", R1, R1));
     ctmk::trace(st, R.p, (int)k4, N.sc + 7);
-    const bool turned = N.spG_n == k4;
+    const bool turned = N.spG_n == k4 && !no_turn;
     const Tn G0 = make_tn(N.spG, {k4, k4});
     const Tn Y = turned ? mm(G0, false, R, false) : R;
     std::vector<JReq> sp{JReq{Y.p, k4, k4, true, {}, {}, {}}};
@@ -1417,6 +1469,8 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
             if (const char* e = std::getenv("CTM_LP_CUTOFF")) x.lp_cut = std::atof(e);            // testing aid
             if (std::getenv("CTM_TRACE_GEMM")) x.trace_gemm = true;                                // testing aid
             if (std::getenv("CTM_NO_WARM_SVD")) x.warm_starts = false;                             // testing aid
+            if (std::getenv("CTM_NO_GEMM_GROUP")) x.no_group = true;                               // testing aid
+            if (std::getenv("CTM_NO_SPEC_TURN")) x.no_turn = true;                                 // testing aid
         }
         HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         for (auto& e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));

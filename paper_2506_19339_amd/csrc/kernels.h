@@ -47,6 +47,21 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
               double beta, double* C, int64_t ldc, int64_t sC, int batch,
               double* ws = nullptr, int64_t ws_cap = 0, hipEvent_t mid = nullptr);
 int gemm_split_plan(int M, int N, int K, int batch, int64_t ws_cap);
+
+// Grouped FP64 GEMM: C_i = alpha op(A_i) op(B_i) for up to kMaxGemmGroup
+// problems of different shapes (same transposes) in one launch, plus one
+// reduction launch when some problem's K range is split (deterministic).
+constexpr int kMaxGemmGroup = 16;
+struct GemmProb {
+    const double* A;
+    const double* B;
+    double* C;
+    int M, N, K;
+    int64_t lda, ldb, ldc;
+};
+void gemm_f64_group(hipStream_t s, bool ta, bool tb, const GemmProb* p, int n, double alpha, double* ws,
+                    int64_t ws_cap, hipEvent_t mid);
+int gemm_group_splits(const GemmProb* p, int n, int64_t ws_cap);   // problems whose K range is split
 // the same product with FP32 (prec 1) or BF16 (prec 2) operands and FP32
 // accumulation; operands and result FP64 in memory
 void gemm_lp(hipStream_t s, int prec, bool ta, bool tb, int M, int N, int K, double alpha,

@@ -38,23 +38,15 @@ constexpr int GT = 64;   // block tile (M and N)
 constexpr int GK = 32;   // K step held in LDS
 constexpr int GL = (GT * GK) / 256;   // elements of each operand a thread stages per step
 
+// One 64x64 tile of out = alpha op(A) op(B) (+ beta out when accumulate),
+// over the K range [kbeg, kend).
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(
-    int M, int N, int K, double alpha,
-    const double* __restrict__ A, int64_t lda, int64_t sA,
-    const double* __restrict__ B, int64_t ldb, int64_t sB,
-    double beta, double* __restrict__ C, int64_t ldc, int64_t sC,
-    int ksplit, int kchunk, double* __restrict__ P)
+__device__ __forceinline__ void gemm_tile(int M, int N, int kbeg, int kend, double alpha,
+                                          const double* __restrict__ A, int64_t lda,
+                                          const double* __restrict__ B, int64_t ldb, double beta,
+                                          bool accumulate, double* __restrict__ out, int64_t ldo, int m0, int n0,
+                                          double (&As)[GK][GT + 1], double (&Bs)[GK][GT + 1])
 {
-    __shared__ double As[GK][GT + 1];
-    __shared__ double Bs[GK][GT + 1];
-    const int z = blockIdx.z;
-    const int bz = z / ksplit, sp = z % ksplit;
-    A += bz * sA;
-    B += bz * sB;
-    const int kbeg = sp * kchunk;
-    const int kend = min(K, kbeg + kchunk);
-    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     dbl4 acc[2][2];
@@ -116,10 +108,6 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         }
         __syncthreads();
     }
-    double* out;
-    int64_t ldo;
-    if (ksplit > 1) { out = P + (int64_t)z * M * N; ldo = N; }
-    else { out = C + bz * sC; ldo = ldc; }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -131,9 +119,77 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
                 if (gm < M && gn < N) {
                     double* c = out + (int64_t)gm * ldo + gn;
                     const double v = alpha * acc[i][j][r];
-                    *c = (beta == 0.0 || ksplit > 1) ? v : v + beta * (*c);
+                    *c = accumulate ? v + beta * (*c) : v;
                 }
             }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    int M, int N, int K, double alpha,
+    const double* __restrict__ A, int64_t lda, int64_t sA,
+    const double* __restrict__ B, int64_t ldb, int64_t sB,
+    double beta, double* __restrict__ C, int64_t ldc, int64_t sC,
+    int ksplit, int kchunk, double* __restrict__ P)
+{
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int z = blockIdx.z;
+    const int bz = z / ksplit, sp = z % ksplit;
+    const int kbeg = sp * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    double* out;
+    int64_t ldo;
+    if (ksplit > 1) { out = P + (int64_t)z * M * N; ldo = N; }
+    else { out = C + bz * sC; ldo = ldc; }
+    gemm_tile<TA, TB>(M, N, kbeg, kend, alpha, A + bz * sA, lda, B + bz * sB, ldb, beta,
+                      !(beta == 0.0 || ksplit > 1), out, ldo, blockIdx.y * GT, blockIdx.x * GT, As, Bs);
+}
+
+// Grouped form: problem i owns the blocks [start[i], start[i + 1]) of a 1-D
+// grid, ks[i] K slices per output tile (slice-major within a tile).  Slices
+// of split problems write to P + poff[i] + slice * M * N.
+struct GemmGroupDev {
+    GemmProb p[kMaxGemmGroup];
+    int start[kMaxGemmGroup + 1];
+    int tn[kMaxGemmGroup];       // tiles along N
+    int ks[kMaxGemmGroup];       // K slices
+    int kc[kMaxGemmGroup];       // K per slice
+    int64_t poff[kMaxGemmGroup]; // partial-product offset (split problems)
+    int n;
+};
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_group_kernel(GemmGroupDev g, double alpha, double* __restrict__ P)
+{
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < g.n && b >= g.start[i + 1]) ++i;
+    const GemmProb q = g.p[i];
+    const int local = b - g.start[i], ks = g.ks[i];
+    const int sp = local % ks, tile = local / ks;
+    const int m0 = (tile / g.tn[i]) * GT, n0 = (tile % g.tn[i]) * GT;
+    const int kbeg = sp * g.kc[i], kend = min(q.K, kbeg + g.kc[i]);
+    double* out = ks > 1 ? P + g.poff[i] + (int64_t)sp * q.M * q.N : q.C;
+    const int64_t ldo = ks > 1 ? q.N : q.ldc;
+    gemm_tile<TA, TB>(q.M, q.N, kbeg, kend, alpha, q.A, q.lda, q.B, q.ldb, 0.0, false, out, ldo, m0, n0, As, Bs);
+}
+
+// C_i = sum of the ks[i] slices, for every split problem i (blockIdx.y)
+__global__ void gemm_group_reduce_kernel(GemmGroupDev g, const double* __restrict__ P)
+{
+    const int i = blockIdx.y;
+    if (i >= g.n || g.ks[i] <= 1) return;
+    const GemmProb q = g.p[i];
+    const int64_t mn = (int64_t)q.M * q.N;
+    const double* p = P + g.poff[i];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int s = 0; s < g.ks[i]; ++s) v += p[s * mn + e];
+        q.C[(e / q.N) * q.ldc + (e % q.N)] = v;
+    }
 }
 
 // C[b][m][n] = sum over the ksplit slices of P[b * ksplit + s][m][n]
@@ -188,6 +244,86 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
         const int64_t total = (int64_t)batch * M * N;
         const int g = (int)std::min<int64_t>((total + 255) / 256, 4096);
         hipLaunchKernelGGL(gemm_reduce_kernel, dim3(g), dim3(256), 0, s, P, M, N, ksplit, C, ldc, sC, total);
+    }
+}
+
+// K slices of every problem of a group: none when the group's tiles fill the
+// chip, else up to ~320 blocks in all, within the workspace
+static void gemm_group_plan(const GemmProb* p, int n, int64_t ws_cap, GemmGroupDev& g)
+{
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) tiles += (int64_t)((p[i].N + GT - 1) / GT) * ((p[i].M + GT - 1) / GT);
+    const int want = tiles >= 160 ? 1 : (int)((320 + tiles - 1) / std::max<int64_t>(tiles, 1));
+    for (int cap = want;; cap = std::max(1, cap / 2)) {
+        int64_t need = 0;
+        for (int i = 0; i < n; ++i) {
+            int s = std::max(1, std::min(cap, p[i].K / (2 * GK)));
+            if (p[i].K < 4 * GK) s = 1;
+            int kc = p[i].K;
+            if (s > 1) {
+                kc = (((p[i].K + s - 1) / s) + GK - 1) / GK * GK;
+                s = (p[i].K + kc - 1) / kc;
+            }
+            g.ks[i] = s;
+            g.kc[i] = std::max(kc, 1);
+            g.poff[i] = need;
+            if (s > 1) need += (int64_t)s * p[i].M * p[i].N;
+        }
+        if (need <= ws_cap || cap == 1) {
+            if (need > ws_cap)
+                for (int i = 0; i < n; ++i) g.ks[i] = 1, g.kc[i] = std::max(p[i].K, 1);
+            return;
+        }
+    }
+}
+
+int gemm_group_splits(const GemmProb* p, int n, int64_t ws_cap)
+{
+    GemmGroupDev g{};
+    gemm_group_plan(p, n, ws_cap, g);
+    int any = 0;
+    for (int i = 0; i < n; ++i) any += g.ks[i] > 1;
+    return any;
+}
+
+void gemm_f64_group(hipStream_t s, bool ta, bool tb, const GemmProb* p, int n, double alpha, double* ws,
+                    int64_t ws_cap, hipEvent_t mid)
+{
+    GemmGroupDev g{};
+    int nz = 0;
+    for (int i = 0; i < n && i < kMaxGemmGroup; ++i)
+        if (p[i].M > 0 && p[i].N > 0) g.p[nz++] = p[i];
+    g.n = nz;
+    if (nz == 0) {
+        if (mid) (void)hipEventRecord(mid, s);
+        return;
+    }
+    gemm_group_plan(g.p, nz, ws ? ws_cap : 0, g);
+    int total = 0, split = 0;
+    int64_t maxmn = 0;
+    for (int i = 0; i < nz; ++i) {
+        const int tm = (g.p[i].M + GT - 1) / GT;
+        g.tn[i] = (g.p[i].N + GT - 1) / GT;
+        g.start[i] = total;
+        total += tm * g.tn[i] * g.ks[i];
+        if (g.ks[i] > 1) {
+            split = 1;
+            maxmn = std::max<int64_t>(maxmn, (int64_t)g.p[i].M * g.p[i].N);
+        }
+    }
+    g.start[nz] = total;
+    if (!ta && !tb)
+        hipLaunchKernelGGL((gemm_f64_group_kernel<false, false>), dim3(total), dim3(256), 0, s, g, alpha, ws);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((gemm_f64_group_kernel<true, false>), dim3(total), dim3(256), 0, s, g, alpha, ws);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((gemm_f64_group_kernel<false, true>), dim3(total), dim3(256), 0, s, g, alpha, ws);
+    else
+        hipLaunchKernelGGL((gemm_f64_group_kernel<true, true>), dim3(total), dim3(256), 0, s, g, alpha, ws);
+    if (mid) (void)hipEventRecord(mid, s);
+    if (split) {
+        const int gx = (int)std::min<int64_t>((maxmn + 255) / 256, 1024);
+        hipLaunchKernelGGL(gemm_group_reduce_kernel, dim3(gx, nz), dim3(256), 0, s, g, ws);
     }
 }
 
@@ -469,8 +605,11 @@ __global__ void sign_fix_kernel(double* __restrict__ UT, double* __restrict__ VT
         }
         __syncthreads();
     }
+    // every thread takes the decision before any thread negates u[jm]
     const int jm = bi[0];
-    if (jm < m && u[jm] < 0.0) {
+    const bool neg = jm < m && u[jm] < 0.0;
+    __syncthreads();
+    if (neg) {
         double* v = VT + (int64_t)row * n;
         for (int j = tid; j < m; j += blockDim.x) u[j] = -u[j];
         for (int j = tid; j < n; j += blockDim.x) v[j] = -v[j];

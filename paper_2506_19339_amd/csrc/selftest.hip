@@ -38,6 +38,55 @@ int ctm_selftest_gemm(int ta, int tb, int M, int N, int K, int batch, const doub
     return rc;
 }
 
+// grouped GEMM of n problems (shapes M[i], N[i], K[i]; dense operands packed
+// one after the other in A, B and C as for ctm_selftest_gemm with batch 1);
+// returns the number of problems whose K range was split through *n_split
+int ctm_selftest_gemm_group(int ta, int tb, int n, const int* M, const int* N, const int* K, const double* A,
+                            const double* B, double* C, long long ws_cap, int* n_split)
+{
+    if (n < 1 || n > ctmk::kMaxGemmGroup) return 1;
+    size_t na = 0, nb = 0, nc = 0;
+    for (int i = 0; i < n; ++i) {
+        na += (size_t)M[i] * K[i];
+        nb += (size_t)K[i] * N[i];
+        nc += (size_t)M[i] * N[i];
+    }
+    double *dA = dev_copy(A, na), *dB = dev_copy(B, nb), *dC = dev_copy<double>(nullptr, nc);
+    double* dW = ws_cap > 0 ? dev_copy<double>(nullptr, (size_t)ws_cap) : nullptr;
+    if (!dA || !dB || !dC || (ws_cap > 0 && !dW)) return 1;
+    ctmk::GemmProb pr[ctmk::kMaxGemmGroup];
+    size_t oa = 0, ob = 0, oc = 0;
+    for (int i = 0; i < n; ++i) {
+        pr[i] = ctmk::GemmProb{dA + oa, dB + ob, dC + oc, M[i], N[i], K[i], ta ? M[i] : K[i], tb ? K[i] : N[i], N[i]};
+        oa += (size_t)M[i] * K[i];
+        ob += (size_t)K[i] * N[i];
+        oc += (size_t)M[i] * N[i];
+    }
+    if (n_split) *n_split = ctmk::gemm_group_splits(pr, n, ws_cap);
+    ctmk::gemm_f64_group(nullptr, ta != 0, tb != 0, pr, n, 1.0, dW, ws_cap, nullptr);
+    int rc = hipMemcpy(C, dC, nc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
+    rc |= hipDeviceSynchronize() != hipSuccess;
+    (void)hipFree(dA);
+    (void)hipFree(dB);
+    (void)hipFree(dC);
+    if (dW) (void)hipFree(dW);
+    return rc;
+}
+
+// sign convention of singular-vector pairs, in place on host copies
+int ctm_selftest_sign_fix(int rows, int m, int n, double* UT, double* VT)
+{
+    double *dU = dev_copy(UT, (size_t)rows * m), *dV = dev_copy(VT, (size_t)rows * n);
+    if (!dU || !dV) return 1;
+    ctmk::sign_fix(nullptr, dU, dV, rows, m, n);
+    int rc = hipMemcpy(UT, dU, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
+    rc |= hipMemcpy(VT, dV, (size_t)rows * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess;
+    rc |= hipDeviceSynchronize() != hipSuccess;
+    (void)hipFree(dU);
+    (void)hipFree(dV);
+    return rc;
+}
+
 // the same with FP32 (prec 1) or BF16 (prec 2) products and FP32 accumulation
 int ctm_selftest_gemm_lp(int prec, int ta, int tb, int M, int N, int K, int batch, const double* A,
                          const double* B, double* C, long long ws_cap)

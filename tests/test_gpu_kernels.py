@@ -26,6 +26,9 @@ def lib():
     L.ctm_selftest_gemm_splits.argtypes = [ctypes.c_int] * 4 + [ctypes.c_longlong]
     L.ctm_selftest_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
     L.ctm_selftest_cholqr.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
+    L.ctm_selftest_sign_fix.argtypes = [ctypes.c_int] * 3 + [dp, dp]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.ctm_selftest_gemm_group.argtypes = [ctypes.c_int] * 3 + [ip, ip, ip, dp, dp, dp, ctypes.c_longlong, ip]
     return L
 
 
@@ -49,6 +52,39 @@ def _gemm_case(lib, ta, tb, M, N, K, batch, ws_cap):
     ref = np.matmul(A.transpose(0, 2, 1) if ta else A, B.transpose(0, 2, 1) if tb else B)
     # FP64 dot products of length K: |error| <= K eps sum|a||b| ~ K eps sqrt(K) for N(0,1) data
     assert np.max(np.abs(C - ref)) <= 4e-16 * K * np.sqrt(K) + 1e-300
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("shapes,cap,split", [
+    ([(128, 500, 500), (128, 1000, 1000), (100, 1000, 1000)], 1 << 22, True),   # subspace products
+    ([(128, 128, 1000), (128, 128, 500), (1, 1, 1)], 1 << 22, True),            # Gram matrices, ragged
+    ([(65, 130, 17), (200, 37, 300), (5, 64, 0)], 0, False),                    # no workspace, K = 0
+    ([(1000, 1000, 64)] * 3, 1 << 22, False),                                   # enough tiles: no split
+    ([(7, 9, 333)] * 16, 1 << 22, True),                                        # the largest group
+])
+def test_grouped_gemm_matches_numpy(lib, ta, tb, shapes, cap, split):
+    rng = np.random.default_rng(len(shapes) + 31 * ta + 7 * tb)
+    As, Bs = [], []
+    for M, N, K in shapes:
+        As.append(rng.standard_normal((K, M) if ta else (M, K)))
+        Bs.append(rng.standard_normal((N, K) if tb else (K, N)))
+    M = np.array([s[0] for s in shapes], dtype=np.int32)
+    N = np.array([s[1] for s in shapes], dtype=np.int32)
+    K = np.array([s[2] for s in shapes], dtype=np.int32)
+    A = np.concatenate([a.ravel() for a in As])
+    B = np.concatenate([b.ravel() for b in Bs])
+    C = np.full(int(np.sum(M * N)), np.nan)
+    ns = ctypes.c_int(-1)
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))  # noqa: E731
+    assert lib.ctm_selftest_gemm_group(ta, tb, len(shapes), ip(M), ip(N), ip(K), _p(A), _p(B), _p(C), cap,
+                                       ctypes.byref(ns)) == 0
+    assert (ns.value > 0) == split
+    off = 0
+    for (m, n, k), a, b in zip(shapes, As, Bs):
+        ref = (a.T if ta else a) @ (b.T if tb else b)
+        got = C[off:off + m * n].reshape(m, n)
+        off += m * n
+        assert np.max(np.abs(got - ref), initial=0.0) <= 4e-16 * k * np.sqrt(k) + 1e-300
 
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
@@ -169,3 +205,21 @@ def test_jacobi_svd_matches_numpy(lib, m, n):
     assert np.all(np.diff(S[:k]) <= 0)
     assert np.allclose((U[:, :k] * S[:k]) @ V[:, :k].T, X, atol=1e-14)
     assert np.allclose(V.T @ V, np.eye(n), atol=1e-13)
+
+
+@pytest.mark.parametrize("rows,m,n", [(1, 1, 1), (100, 5000, 1000), (300, 257, 3), (64, 64, 64)])
+def test_sign_fix_flips_whole_rows(lib, rows, m, n):
+    """Each row pair (u_i, v_i) is negated as a whole exactly when the entry of
+    u_i with the largest magnitude (first on ties) is negative; the largest
+    entry is placed in the lane that negates first, for every row."""
+    rng = np.random.default_rng(rows + m + n)
+    U = rng.standard_normal((rows, m))
+    V = rng.standard_normal((rows, n))
+    for i in range(rows):
+        j = (i * 37) % m
+        U[i, j] = (-1.0) ** i * (np.max(np.abs(U[i])) + 1.0)
+    U0, V0 = U.copy(), V.copy()
+    assert lib.ctm_selftest_sign_fix(rows, m, n, _p(U), _p(V)) == 0
+    for i in range(rows):
+        s = -1.0 if U0[i, np.argmax(np.abs(U0[i]))] < 0 else 1.0
+        assert np.array_equal(U[i], s * U0[i]) and np.array_equal(V[i], s * V0[i]), i
