@@ -163,8 +163,6 @@ struct Net {
     double* sc = nullptr;            // scalars: n1 n2h n2v n0 | lk flag | tr
     double* E = nullptr;             // bra environment, 2 D^4
     double* sv = nullptr;            // spectrum buffer
-    double* spG = nullptr;           // right singular vectors of the last spectrum matrix (rows)
-    int64_t spG_n = 0;               // their size, 0: none yet
 };
 
 // per-kernel-class launch statistics (CTM_FLAG_PROFILE): HIP events on the
@@ -225,7 +223,7 @@ struct Worker {
     int64_t trace_perm = 0;          // testing aid: log permutes of at least this many elements
     bool trace_gemm = false;         // testing aid: log GEMM shapes
     bool no_group = false;           // testing aid: one launch per product in mm_group
-    bool no_turn = false;            // testing aid: spectrum Jacobi on the plain matrix
+    bool trace_sweeps = false;       // testing aid: log the sweeps of every Jacobi job (profile mode)
     bool warm_starts = true;         // keep each slot's Ritz basis for the next move
     double last_delta = 1.0;         // spectrum change of this network's last move (host copy)
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
@@ -311,6 +309,8 @@ struct Worker {
         HIPCHK(hipStreamSynchronize(st));
         for (size_t i = 0; i < sw.size(); ++i) {
             const JobShape& j = sweep_jobs[i];
+            if (trace_sweeps)
+                std::fprintf(stderr, "sweeps %lld %lld %d %d\n", (long long)j.m, (long long)j.n, (int)j.v, sw[i]);
             kstat[1].flops += (double)sw[i] * 0.5 * (double)j.n * (double)(j.n - 1) *
                               (12.0 * (double)j.m + (j.v ? 6.0 * (double)j.n : 0.0));
         }
@@ -1048,25 +1048,14 @@ void Worker::step(Net& N, int64_t chi)
     normalize(Ti_n);
     normalize(Tb_n);
 
-    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form).
-    // The rows of the matrix are first combined by the right singular vectors
-    // of the last move's matrix (an orthogonal factor, so the singular values
-    // are unchanged).  In the sign-fixed bond gauge of a settling environment
-    // the combined rows are already close to orthogonal and the one-sided
-    // Jacobi needs few sweeps; the accumulated factor is kept for the next move.
+    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form)
     Prec spec64(*this, CTM_FP64);
     Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
     Tn R = mat(ctr("ab,bc->ac", R1, R1));
     ctmk::trace(st, R.p, (int)k4, N.sc + 7);
-    const bool turned = N.spG_n == k4 && !no_turn;
-    const Tn G0 = make_tn(N.spG, {k4, k4});
-    const Tn Y = turned ? mm(G0, false, R, false) : R;
-    std::vector<JReq> sp{JReq{Y.p, k4, k4, true, {}, {}, {}}};
+    std::vector<JReq> sp{JReq{R.p, k4, k4, false, {}, {}, {}}};
     jacobi_batch(sp);
     ctmk::spectrum_delta(st, sp[0].S.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
-    const Tn G1 = turned ? mm(sp[0].V, false, G0, false) : sp[0].V;
-    ctmk::copy(st, G1.p, N.spG, k4 * k4);
-    N.spG_n = k4;
 
     // ---- store
     N.xbk = k4;
@@ -1250,14 +1239,12 @@ static void init_net(ctm_ctx* c, Net& N, int d)
     N.sc = c->keep(16);
     N.E = c->keep(2 * D * D * D * D);
     N.sv = c->keep(x);
-    N.spG = c->keep(x * x);
 }
 
 static void reset_env(Worker& W, Net& N, int D)
 {
     const int64_t d = N.d;
     N.xbk = N.xki = N.xib = 1;
-    N.spG_n = 0;
     W.last_delta = 1.0;
     ctmk::fill(W.st, N.C1, 1, 1.0);
     ctmk::fill(W.st, N.C4, 1, 1.0);
@@ -1470,7 +1457,7 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
             if (std::getenv("CTM_TRACE_GEMM")) x.trace_gemm = true;                                // testing aid
             if (std::getenv("CTM_NO_WARM_SVD")) x.warm_starts = false;                             // testing aid
             if (std::getenv("CTM_NO_GEMM_GROUP")) x.no_group = true;                               // testing aid
-            if (std::getenv("CTM_NO_SPEC_TURN")) x.no_turn = true;                                 // testing aid
+            if (std::getenv("CTM_TRACE_SWEEPS")) x.trace_sweeps = true;                            // testing aid
         }
         HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         for (auto& e : c->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));

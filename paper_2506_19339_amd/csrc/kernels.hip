@@ -1357,74 +1357,59 @@ __global__ __launch_bounds__(1024) void jacobi_small_kernel(JacobiBatch jobs, in
 // even and (2p+1, 2p+2) when s is odd, rotates each pair and swaps the two
 // columns' positions.  After ne steps the order is reversed and every pair has
 // met once (odd-even transposition sort of a reversed sequence), so a sweep is
-// ne steps.  Pair p is held in registers by 16 lanes: lanes 0-7 hold 16 rows
-// each of its two columns of X, lanes 8-15 16 rows each of its two columns of
-// V.  A 512-thread workgroup gives each 16-lane group two pairs (p and p + 32),
-// so that the 128 doubles a lane holds fit in registers.  Between steps each
+// ne steps.  Pair p is held in registers by the 16 lanes of group p of a
+// 1024-thread workgroup: lane l holds rows l, l + 16, ..., l + 112 of both
+// columns of X and of V (32 doubles), so all 16 lanes share the dot products
+// and the four waves per SIMD hide each other's latency.  Between steps each
 // pair hands one column to a neighbour through LDS: per step half of the
 // columns move and nothing else touches memory.
 constexpr int kRegJacobi = 128;
-constexpr int kRegThreads = 512;
+constexpr int kRegThreads = 1024;
 
 template <bool WANT_V>
 __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch jobs, int max_sweeps)
 {
-    constexpr int NP = kRegJacobi / 2;             // pairs
-    constexpr int NG = kRegThreads / 16;           // 16-lane groups
-    constexpr int PP = NP / NG;                    // pairs per group
-    __shared__ __attribute__((aligned(16))) double xfer[NP][2 * kRegJacobi];
-    __shared__ __attribute__((aligned(16))) double park[2 * kRegJacobi];
+    constexpr int NP = kRegJacobi / 2;             // pairs = 16-lane groups
+    constexpr int RL = kRegJacobi / 16;            // rows per lane
+    constexpr int XS = 2 * kRegJacobi + 16;        // LDS column slot: X rows, V rows, pad
+    static_assert(NP * 16 == kRegThreads, "one pair per 16-lane group");
+    __shared__ __attribute__((aligned(16))) double xfer[NP][XS];
+    __shared__ __attribute__((aligned(16))) double park[XS];
     __shared__ int xid[NP];
     __shared__ int park_id;
     __shared__ double sig[kRegJacobi + 1];
     __shared__ int rnk[kRegJacobi + 1];
-    __shared__ double gsum[NG];
+    __shared__ double gsum[NP];
     __shared__ int rotated;
     __shared__ double fro2;
     const JacobiJob jb = jobs.job[blockIdx.x];
     const int m = jb.m, n = jb.n;
     const int ne = n + (n & 1);
     const int P = ne / 2;
-    const int tid = threadIdx.x, g = tid >> 4, l16 = tid & 15, half = l16 >> 3, sub = l16 & 7;
-    const int rows = half == 0 ? m : n;      // rows of the part this lane holds
+    const int tid = threadIdx.x, p = tid >> 4, l16 = tid & 15;
 
-    double a[PP][16], b[PP][16];
-    int ia[PP], ib[PP];
+    // columns at positions 2p (a) and 2p+1 (b): X rows in ax/bx, V rows in av/bv
+    double ax[RL], bx[RL], av[RL], bv[RL];
+    int ia = 2 * p, ib = 2 * p + 1;
 #pragma unroll
-    for (int q = 0; q < PP; ++q) {
-        const int pr = g + NG * q;
-        ia[q] = 2 * pr;
-        ib[q] = 2 * pr + 1;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int r = sub + 8 * u;
-            double va = 0.0, vb = 0.0;
-            if (pr < P && r < rows) {
-                if (half == 0) {
-                    va = ia[q] < n ? jb.X[(int64_t)ia[q] * m + r] : 0.0;
-                    vb = ib[q] < n ? jb.X[(int64_t)ib[q] * m + r] : 0.0;
-                } else if (WANT_V) {
-                    va = (r == ia[q]) ? 1.0 : 0.0;
-                    vb = (r == ib[q]) ? 1.0 : 0.0;
-                }
-            }
-            a[q][u] = va;
-            b[q][u] = vb;
-        }
+    for (int u = 0; u < RL; ++u) {
+        const int r = l16 + 16 * u;
+        const bool live = p < P;
+        ax[u] = (live && r < m && ia < n) ? jb.X[(int64_t)ia * m + r] : 0.0;
+        bx[u] = (live && r < m && ib < n) ? jb.X[(int64_t)ib * m + r] : 0.0;
+        av[u] = (WANT_V && live && r < n && r == ia) ? 1.0 : 0.0;
+        bv[u] = (WANT_V && live && r < n && r == ib) ? 1.0 : 0.0;
     }
     {
         double t = 0.0;
-        if (half == 0)
 #pragma unroll
-            for (int q = 0; q < PP; ++q)
-#pragma unroll
-                for (int u = 0; u < 16; ++u) t += a[q][u] * a[q][u] + b[q][u] * b[q][u];
+        for (int u = 0; u < RL; ++u) t += ax[u] * ax[u] + bx[u] * bx[u];
         t = sum16(t);
-        if (l16 == 0) gsum[g] = t;
+        if (l16 == 0) gsum[p] = t;
         __syncthreads();
         if (tid == 0) {
             double f = 0.0;
-            for (int i = 0; i < NG; ++i) f += gsum[i];
+            for (int i = 0; i < NP; ++i) f += gsum[i];
             fro2 = f;
         }
         __syncthreads();
@@ -1433,47 +1418,60 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
     const double tol = 2.0 * sqrt((double)m) * 2.220446049250313e-16;
     const double tol2 = tol * tol;
 
-    // rotation of the pairs held in (L, R), then swap of their positions:
+    // rotation of the pair held in (L, R), then swap of their positions:
     // L <- s L + c R, R <- c L - s R; lid / rid follow the columns
-    auto rotate = [&](double (&L)[PP][16], double (&R)[PP][16], int (&lid)[PP], int (&rid)[PP], bool odd) {
-        double al[PP], be[PP], ga[PP];
+    auto rotate = [&](double (&Lx)[RL], double (&Rx)[RL], double (&Lv)[RL], double (&Rv)[RL], int& lid, int& rid,
+                      bool odd) {
+        double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int q = 0; q < PP; ++q) {
-            al[q] = be[q] = ga[q] = 0.0;
-            if (half == 0) {
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    al[q] += L[q][u] * L[q][u];
-                    be[q] += R[q][u] * R[q][u];
-                    ga[q] += L[q][u] * R[q][u];
-                }
-            }
-            al[q] = sum16(al[q]);
-            be[q] = sum16(be[q]);
-            ga[q] = sum16(ga[q]);
+        for (int u = 0; u < RL; ++u) {
+            al += Lx[u] * Lx[u];
+            be += Rx[u] * Rx[u];
+            ga += Lx[u] * Rx[u];
+        }
+        al = sum16(al);
+        be = sum16(be);
+        ga = sum16(ga);
+        if (!(p < P && (!odd || p < P - 1))) return;
+        double c = 1.0, sn = 0.0;
+        if (ga != 0.0 && al > noise2 && be > noise2 && ga * ga > tol2 * (al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = c * t;
+            if (l16 == 0) rotated = 1;
         }
 #pragma unroll
-        for (int q = 0; q < PP; ++q) {
-            const int pr = g + NG * q;
-            if (!(pr < P && (!odd || pr < P - 1))) continue;
-            double c = 1.0, sn = 0.0;
-            if (ga[q] != 0.0 && al[q] > noise2 && be[q] > noise2 && ga[q] * ga[q] > tol2 * (al[q] * be[q])) {
-                const double zeta = (be[q] - al[q]) / (2.0 * ga[q]);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                c = 1.0 / sqrt(1.0 + t * t);
-                sn = c * t;
-                if (l16 == 0) rotated = 1;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const double x = L[q][u], y = R[q][u];
-                L[q][u] = sn * x + c * y;
-                R[q][u] = c * x - sn * y;
-            }
-            const int t = lid[q];
-            lid[q] = rid[q];
-            rid[q] = t;
+        for (int u = 0; u < RL; ++u) {
+            const double x = Lx[u], y = Rx[u];
+            Lx[u] = sn * x + c * y;
+            Rx[u] = c * x - sn * y;
         }
+        if (WANT_V) {
+#pragma unroll
+            for (int u = 0; u < RL; ++u) {
+                const double x = Lv[u], y = Rv[u];
+                Lv[u] = sn * x + c * y;
+                Rv[u] = c * x - sn * y;
+            }
+        }
+        const int t = lid;
+        lid = rid;
+        rid = t;
+    };
+    auto put = [&](double* dst, const double (&x)[RL], const double (&v)[RL]) {
+#pragma unroll
+        for (int u = 0; u < RL; ++u) dst[l16 + 16 * u] = x[u];
+        if (WANT_V)
+#pragma unroll
+            for (int u = 0; u < RL; ++u) dst[kRegJacobi + l16 + 16 * u] = v[u];
+    };
+    auto get = [&](const double* src, double (&x)[RL], double (&v)[RL]) {
+#pragma unroll
+        for (int u = 0; u < RL; ++u) x[u] = src[l16 + 16 * u];
+        if (WANT_V)
+#pragma unroll
+            for (int u = 0; u < RL; ++u) v[u] = src[kRegJacobi + l16 + 16 * u];
     };
 
     // Registers a and b trade roles between the two halves of a double step:
@@ -1485,56 +1483,37 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int step = 0; step < ne; step += 2) {
-            rotate(a, b, ia, ib, false);
+            rotate(ax, bx, av, bv, ia, ib, false);
             // even -> odd: send position 2p (a) to p-1 (p = 0: park), receive 2p+2 into a
-#pragma unroll
-            for (int q = 0; q < PP; ++q) {
-                const int pr = g + NG * q;
-                if (pr >= P) continue;
-                double* dst = pr == 0 ? park : xfer[pr];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) dst[half * kRegJacobi + sub + 8 * u] = a[q][u];
+            if (p < P) {
+                put(p == 0 ? park : xfer[p], ax, av);
                 if (l16 == 0) {
-                    if (pr == 0) park_id = ia[q];
-                    else xid[pr] = ia[q];
+                    if (p == 0) park_id = ia;
+                    else xid[p] = ia;
                 }
             }
             __syncthreads();
-#pragma unroll
-            for (int q = 0; q < PP; ++q) {
-                const int pr = g + NG * q;
-                if (pr >= P) continue;
-                if (pr + 1 < P) {
-                    const double* srcp = xfer[pr + 1];
-#pragma unroll
-                    for (int u = 0; u < 16; ++u) a[q][u] = srcp[half * kRegJacobi + sub + 8 * u];
-                    ia[q] = xid[pr + 1];
+            if (p < P) {
+                if (p + 1 < P) {
+                    get(xfer[p + 1], ax, av);
+                    ia = xid[p + 1];
                 } else {
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) a[q][u] = 0.0;
-                    ia[q] = -1;
+                    for (int u = 0; u < RL; ++u) ax[u] = av[u] = 0.0;
+                    ia = -1;
                 }
             }
             __syncthreads();
-            rotate(b, a, ib, ia, true);
+            rotate(bx, ax, bv, av, ib, ia, true);
             // odd -> even: send position 2p+2 (a) to p+1, receive 2p into a (p = 0: park)
-#pragma unroll
-            for (int q = 0; q < PP; ++q) {
-                const int pr = g + NG * q;
-                if (pr + 1 >= P) continue;
-#pragma unroll
-                for (int u = 0; u < 16; ++u) xfer[pr][half * kRegJacobi + sub + 8 * u] = a[q][u];
-                if (l16 == 0) xid[pr] = ia[q];
+            if (p + 1 < P) {
+                put(xfer[p], ax, av);
+                if (l16 == 0) xid[p] = ia;
             }
             __syncthreads();
-#pragma unroll
-            for (int q = 0; q < PP; ++q) {
-                const int pr = g + NG * q;
-                if (pr >= P) continue;
-                const double* srcp = pr == 0 ? park : xfer[pr - 1];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) a[q][u] = srcp[half * kRegJacobi + sub + 8 * u];
-                ia[q] = pr == 0 ? park_id : xid[pr - 1];
+            if (p < P) {
+                get(p == 0 ? park : xfer[p - 1], ax, av);
+                ia = p == 0 ? park_id : xid[p - 1];
             }
             __syncthreads();
         }
@@ -1546,21 +1525,18 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
         if (sweep + 1 == max_sweeps && jb.sweeps && tid == 0) jb.sweeps[0] = max_sweeps;
     }
     // singular values = column norms, by original column id (the padding column has id n)
-#pragma unroll
-    for (int q = 0; q < PP; ++q) {
-        const int pr = g + NG * q;
+    {
         double na = 0.0, nb = 0.0;
-        if (half == 0)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                na += a[q][u] * a[q][u];
-                nb += b[q][u] * b[q][u];
-            }
+        for (int u = 0; u < RL; ++u) {
+            na += ax[u] * ax[u];
+            nb += bx[u] * bx[u];
+        }
         na = sum16(na);
         nb = sum16(nb);
-        if (pr < P && l16 == 0) {
-            if (ia[q] >= 0 && ia[q] < n) sig[ia[q]] = sqrt(na);
-            if (ib[q] >= 0 && ib[q] < n) sig[ib[q]] = sqrt(nb);
+        if (p < P && l16 == 0) {
+            if (ia >= 0 && ia < n) sig[ia] = sqrt(na);
+            if (ib >= 0 && ib < n) sig[ib] = sqrt(nb);
         }
     }
     __syncthreads();
@@ -1574,26 +1550,21 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
         rnk[j] = r;
     }
     __syncthreads();
+    if (p >= P) return;
 #pragma unroll
-    for (int q = 0; q < PP; ++q) {
-        const int pr = g + NG * q;
-        if (pr >= P) continue;
+    for (int side = 0; side < 2; ++side) {
+        const int id = side == 0 ? ia : ib;
+        if (id < 0 || id >= n) continue;
+        const int dst = rnk[id];
+        const double sj = sig[id];
+        const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int id = side == 0 ? ia[q] : ib[q];
-            if (id < 0 || id >= n) continue;
-            const int dst = rnk[id];
-            const double sj = sig[id];
-            const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int r = sub + 8 * u;
-                const double v = side == 0 ? a[q][u] : b[q][u];
-                if (half == 0 && r < m) jb.U[(int64_t)dst * m + r] = v * inv;
-                if (WANT_V && half == 1 && r < n) jb.V[(int64_t)dst * n + r] = v;
-            }
-            if (l16 == 0) jb.S[dst] = sj;
+        for (int u = 0; u < RL; ++u) {
+            const int r = l16 + 16 * u;
+            if (r < m) jb.U[(int64_t)dst * m + r] = (side == 0 ? ax[u] : bx[u]) * inv;
+            if (WANT_V && r < n) jb.V[(int64_t)dst * n + r] = side == 0 ? av[u] : bv[u];
         }
+        if (l16 == 0) jb.S[dst] = sj;
     }
 }
 
