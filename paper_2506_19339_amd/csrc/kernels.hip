@@ -1673,94 +1673,166 @@ __global__ __launch_bounds__(1024) void cholqr_kernel(CholBatch jobs, double shi
     }
 }
 
-// k <= 128: the same elimination with the matrix held in registers.  Row i
-// lives in wave i % 16 (slot i / 16), each lane holding the entries e = lane
-// and lane + 64 of that row of the Schur complement S and of the elimination
-// matrix X.  Step j: the owner of row j publishes S_j and X_j through LDS
-// (double-buffered, one barrier per step), and every row i > j applies
-// S_i -= f S_j, X_i -= f X_j with f = S_ji / S_jj (full rows keep S symmetric
-// up to rounding, so S_ji stands for S_ij).  LDS traffic per step is one row
-// pair, not the whole matrix.
+// k <= 128: the same elimination, blocked, with the rows in registers.
+// Waves 1-15 own the rows (row i in wave 1 + i % 15, slot i / 15; each lane
+// holds the entries e = lane and lane + 64 of its rows of the Schur
+// complement S and of the elimination matrix X).  Per block of kCholB columns
+// j0 .. j0+nb-1: the owners publish the block's rows to LDS; wave 0 (the panel
+// wave) eliminates within the block in registers, broadcasting the factors
+// with readlane, and writes back the block rows as they stand at their own
+// pivot step together with the reciprocal pivots; every row below the block
+// then applies the nb eliminations S_i -= f S_t, X_i -= f X_t with
+// f = S_t[i] / p_t (S_t[i] = S_i[t] by symmetry of the Schur complement).
+// Two barriers per block instead of one per column; the block buffers are
+// double-buffered.  Entries that are zero by structure are skipped: S_i[e]
+// for e < j0 (eliminated columns) and X_t[e] for e >= j0 + nb.
 constexpr int kCholReg = 128;
+constexpr int kCholB = 8;
+constexpr int kCholOwners = 15;
+constexpr int kCholSlots = (kCholReg + kCholOwners - 1) / kCholOwners;
+
+__device__ inline double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
 
 __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double shift)
 {
     __shared__ double dsc[kCholReg];
-    __shared__ double rowS[2][kCholReg];
-    __shared__ double rowX[2][kCholReg];
+    __shared__ double bS[2][kCholB][kCholReg];
+    __shared__ double bX[2][kCholB][kCholReg];
+    __shared__ double binv[2][kCholB];
     const CholJob jb = jobs.job[blockIdx.x];
     const int k = jb.k;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = 16, SLOTS = kCholReg / NW;
+    const int ow = wave - 1;                       // owner index; -1: the panel wave
     for (int i = tid; i < k; i += blockDim.x) {
         const double v = jb.G[(int64_t)i * k + i];
         dsc[i] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
     }
     __syncthreads();
-    double S[SLOTS][2], Xr[SLOTS][2];
+    double S[kCholSlots][2], Xr[kCholSlots][2];
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const int i = wave + NW * s;
+    for (int s = 0; s < kCholSlots; ++s) {
+        const int i = ow + kCholOwners * s;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int e = lane + 64 * u;
-            const bool ok = i < k && e < k;
+            const bool ok = ow >= 0 && i < k && e < k;
             S[s][u] = ok ? jb.G[(int64_t)i * k + e] * dsc[i] * dsc[e] + (i == e ? shift : 0.0) : 0.0;
             Xr[s][u] = (ok && i == e) ? 1.0 : 0.0;
         }
     }
-    for (int j = 0; j < k; ++j) {
-        const int buf = j & 1;
-        if (wave == j % NW) {
-            const int sj = j / NW;
+    int buf = 0;
+    for (int j0 = 0; j0 < k; j0 += kCholB, buf ^= 1) {
+        const int nb = min(kCholB, k - j0);
+        // the owners publish the block's rows (eliminated by all earlier blocks)
+        if (ow >= 0) {
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s)
-                if (s == sj) {
+            for (int s = 0; s < kCholSlots; ++s) {
+                const int i = ow + kCholOwners * s;
+                if (i >= j0 && i < j0 + nb) {
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
-                        const int e = lane + 64 * u;
-                        if (e < k) {
-                            rowS[buf][e] = S[s][u];
-                            rowX[buf][e] = Xr[s][u];
-                        }
+                        bS[buf][i - j0][lane + 64 * u] = S[s][u];
+                        bX[buf][i - j0][lane + 64 * u] = Xr[s][u];
                     }
                 }
+            }
         }
         __syncthreads();
-        const double pj = rowS[buf][j];
-        const double inv = pj > 0.0 ? 1.0 / pj : 0.0;
-        double sj[2], xj[2];
+        if (ow < 0) {
+            // panel wave: elimination within the block, in the registers that
+            // hold rows in the owner waves (the panel wave owns none)
+            static_assert(kCholB <= kCholSlots, "block rows fit the row registers");
+            double (&rs)[kCholSlots][2] = S;
+            double (&rx)[kCholSlots][2] = Xr;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = lane + 64 * u;
-            sj[u] = e < k ? rowS[buf][e] : 0.0;
-            xj[u] = e < k ? rowX[buf][e] : 0.0;
-        }
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            const int i = wave + NW * s;
-            if (i > j && i < k) {
-                const double f = rowS[buf][i] * inv;   // S_ij = S_ji (S symmetric)
+            for (int t = 0; t < kCholB; ++t)
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    S[s][u] -= f * sj[u];
-                    Xr[s][u] -= f * xj[u];
+                    rs[t][u] = t < nb ? bS[buf][t][lane + 64 * u] : 0.0;
+                    rx[t][u] = t < nb ? bX[buf][t][lane + 64 * u] : 0.0;
+                }
+            const bool hi = j0 >= 64;                 // a block never straddles entry 64
+            const int el = j0 & 63;
+#pragma unroll
+            for (int t = 0; t < kCholB; ++t) {
+                if (t >= nb) break;
+                const double piv = readlane_f64(hi ? rs[t][1] : rs[t][0], el + t);
+                const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+                if (lane == 0) binv[buf][t] = inv;
+#pragma unroll
+                for (int t2 = t + 1; t2 < kCholB; ++t2) {
+                    if (t2 >= nb) break;
+                    const double f = readlane_f64(hi ? rs[t2][1] : rs[t2][0], el + t) * inv;
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        rs[t2][u] -= f * rs[t][u];
+                        rx[t2][u] -= f * rx[t][u];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kCholB; ++t)
+                if (t < nb)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        bS[buf][t][lane + 64 * u] = rs[t][u];
+                        bX[buf][t][lane + 64 * u] = rx[t][u];
+                    }
+        }
+        __syncthreads();
+        if (ow >= 0) {
+            // the block's own rows take their eliminated values
+#pragma unroll
+            for (int s = 0; s < kCholSlots; ++s) {
+                const int i = ow + kCholOwners * s;
+                if (i >= j0 && i < j0 + nb) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        S[s][u] = bS[buf][i - j0][lane + 64 * u];
+                        Xr[s][u] = bX[buf][i - j0][lane + 64 * u];
+                    }
+                }
+            }
+            // rows below the block: nb eliminations each
+            const bool s_lo = j0 < 64;                // S entries 0-63 still live
+            const bool x_hi = j0 + nb > 64;           // X_t entries 64-127 can be nonzero
+#pragma unroll
+            for (int t = 0; t < kCholB; ++t) {
+                if (t >= nb) break;
+                const double s0 = s_lo ? bS[buf][t][lane] : 0.0, s1 = bS[buf][t][lane + 64];
+                const double x0 = bX[buf][t][lane], x1 = x_hi ? bX[buf][t][lane + 64] : 0.0;
+                const double inv = binv[buf][t];
+#pragma unroll
+                for (int s = 0; s < kCholSlots; ++s) {
+                    const int i = ow + kCholOwners * s;
+                    if (i >= j0 + nb && i < k) {
+                        const double f = bS[buf][t][i] * inv;
+                        if (s_lo) S[s][0] -= f * s0;
+                        S[s][1] -= f * s1;
+                        Xr[s][0] -= f * x0;
+                        if (x_hi) Xr[s][1] -= f * x1;
+                    }
                 }
             }
         }
     }
     // pivots p_i = S_ii; T[i][c] = p_i^-1/2 X_ic d_c
+    if (ow < 0) return;
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const int i = wave + NW * s;
-        const double pii = __shfl((i >> 6) ? S[s][1] : S[s][0], i & 63, 64);
+    for (int s = 0; s < kCholSlots; ++s) {
+        const int i = ow + kCholOwners * s;
+        if (i >= k) continue;
+        const double pii = readlane_f64((i >> 6) ? S[s][1] : S[s][0], i & 63);
         const double di = pii > 0.0 ? 1.0 / sqrt(pii) : 0.0;
-        if (i < k) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int c = lane + 64 * u;
-                if (c < k) jb.T[(int64_t)i * k + c] = c <= i ? di * Xr[s][u] * dsc[c] : 0.0;
-            }
+        for (int u = 0; u < 2; ++u) {
+            const int c = lane + 64 * u;
+            if (c < k) jb.T[(int64_t)i * k + c] = c <= i ? di * Xr[s][u] * dsc[c] : 0.0;
         }
     }
 }
