@@ -178,7 +178,8 @@ struct KStat {
 constexpr int kJacobiExact = 64;    // exact Jacobi SVD when min(m, n) <= this
 constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resident)
 constexpr int kOversample = 16;
-constexpr int kWarmPowerIters = 4;  // power steps when every subspace starts from last move's
+constexpr int kWarmPowerIters = 2;  // power steps when every subspace starts from last move's basis
+                                    // (the iteration continues across moves)
 constexpr double kWarmGate = 1e-5;  // spectrum change per move below which the last bases are reused
 constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resident Jacobi)
 // relative pseudo-inverse cutoff of S^1/2: singular values of rho_B rho_T below
