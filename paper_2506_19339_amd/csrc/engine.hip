@@ -180,7 +180,7 @@ constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resid
 constexpr int kOversample = 16;
 constexpr int kWarmPowerIters = 2;  // power steps when every subspace starts from last move's basis
                                     // (the iteration continues across moves)
-constexpr double kWarmGate = 1e-5;  // spectrum change per move below which the last bases are reused
+constexpr double kWarmGate = 1e-3;  // spectrum change per move below which the last bases are reused
 constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resident Jacobi)
 // relative pseudo-inverse cutoff of S^1/2: singular values of rho_B rho_T below
 // 1e-8 of the largest are dropped.  The subspace factorisation squares the
