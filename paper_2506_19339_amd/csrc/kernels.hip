@@ -125,7 +125,7 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int kbeg, int kend, doub
 }
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(
+__global__ __launch_bounds__(256, 4) void gemm_f64_kernel(
     int M, int N, int K, double alpha,
     const double* __restrict__ A, int64_t lda, int64_t sA,
     const double* __restrict__ B, int64_t ldb, int64_t sB,
@@ -160,7 +160,7 @@ struct GemmGroupDev {
 };
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_f64_group_kernel(GemmGroupDev g, double alpha, double* __restrict__ P)
+__global__ __launch_bounds__(256, 4) void gemm_f64_group_kernel(GemmGroupDev g, double alpha, double* __restrict__ P)
 {
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
@@ -210,8 +210,12 @@ __global__ void gemm_reduce_kernel(const double* __restrict__ P, int M, int N, i
 int gemm_split_plan(int M, int N, int K, int batch, int64_t ws_cap)
 {
     const int64_t tiles = (int64_t)((N + GT - 1) / GT) * ((M + GT - 1) / GT) * batch;
-    if (tiles >= 160 || K < 4 * GK) return 1;
-    int s = (int)std::min<int64_t>((320 + tiles - 1) / tiles, K / (2 * GK));
+    int s = 1;
+    if (tiles < 160 && K >= 4 * GK)
+        s = (int)std::min<int64_t>((320 + tiles - 1) / tiles, K / (2 * GK));   // few tiles: ~320 blocks
+    else if (tiles < 1024 && K >= 16 * GK)
+        s = (int)std::min<int64_t>((1024 + tiles - 1) / tiles, K / (4 * GK));  // long K: ~4 blocks per CU
+    if (s <= 1) return 1;
     while (s > 1 && (int64_t)s * M * N * batch > ws_cap) --s;
     return std::max(s, 1);
 }
