@@ -212,6 +212,9 @@ struct Worker {
     int D = 0;
     const double* A = nullptr;       // D4-projected A, owned by the context
     hipStream_t st = nullptr;        // created by the context (default priority)
+    hipStream_t st_side = nullptr;   // side stream of the convergence spectrum (default priority)
+    hipEvent_t ev_side_fork = nullptr, ev_side_done = nullptr;
+    bool on_side = false, side_pending = false;
     Arena ws;
     std::vector<void*> owned;        // persistent allocations of this worker
     double* part = nullptr;          // reduction partials
@@ -247,6 +250,9 @@ struct Worker {
         A = a;
         profiling = (c.flags & CTM_FLAG_PROFILE) != 0;
         HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&st_side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ev_side_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev_side_done, hipEventDisableTiming));
         part = keep(ctmk::kRedBlocks);
         scal = keep(16);
         icount = (int*)keep(kMaxBatch);
@@ -269,8 +275,45 @@ struct Worker {
         }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
+        if (st_side) {
+            (void)hipStreamSynchronize(st_side);
+            (void)hipStreamDestroy(st_side);
+        }
+        if (ev_side_fork) (void)hipEventDestroy(ev_side_fork);
+        if (ev_side_done) (void)hipEventDestroy(ev_side_done);
+        st_side = nullptr;
+        ev_side_fork = ev_side_done = nullptr;
         if (st) (void)hipStreamDestroy(st);
         st = nullptr;
+    }
+
+    // Work enqueued between side_begin and side_end goes to the side stream
+    // (after everything enqueued on the worker stream so far) and runs
+    // concurrently with what the worker stream does next, until side_wait.
+    // The side work must not use the split-K workspace or the reduction
+    // scratch of the worker stream.  In profile mode everything stays on the
+    // worker stream.
+    void side_begin()
+    {
+        if (profiling) return;
+        HIPCHK(hipEventRecord(ev_side_fork, st));
+        HIPCHK(hipStreamWaitEvent(st_side, ev_side_fork, 0));
+        std::swap(st, st_side);
+        on_side = true;
+    }
+    void side_end()
+    {
+        if (!on_side) return;
+        HIPCHK(hipEventRecord(ev_side_done, st));
+        std::swap(st, st_side);
+        on_side = false;
+        side_pending = true;
+    }
+    void side_wait()
+    {
+        if (!side_pending) return;
+        HIPCHK(hipStreamWaitEvent(st, ev_side_done, 0));
+        side_pending = false;
     }
 
     hipEvent_t ev_get()
@@ -1023,6 +1066,31 @@ void Worker::step(Net& N, int64_t chi)
     Tn PibT = ctr("ncao,cxbq->nxaoqb", P6T, P3T);       // [n, chi, A, O, q, B]
     Tn PibB = ctr("xbqc,caon->xaoqbn", P3B, P6B);       // [chi, A, O, q, B, n]
 
+    // ---- corners: second-stage projectors on the stage-1 renormalised corners
+    Tn W1 = ctr("cdfqre,Xqre->cdfX", C1p, P4T);
+    Tn C1_n = mat(ctr("cdfX,Ycdf->XY", W1, P4T));
+    Tn W4 = ctr("cwhXyi,cwhx->xXyi", C4p, P4B);
+    Tn C4_n = mat(ctr("xXyi,Xyiz->xz", W4, P4B));
+    ctmk::symmetrize(st, C1_n.p, (int)k4);
+    ctmk::symmetrize(st, C4_n.p, (int)k4);
+    normalize(C1_n);
+    normalize(C4_n);
+
+    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form).
+    // The two products run on this stream; the Jacobi SVD and the spectrum
+    // change run on the side stream while this stream renormalises the edges.
+    {
+        Prec spec64(*this, CTM_FP64);
+        Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
+        Tn R = mat(ctr("ab,bc->ac", R1, R1));
+        ctmk::trace(st, R.p, (int)k4, N.sc + 7);
+        side_begin();
+        std::vector<JReq> sp{JReq{R.p, k4, k4, false, {}, {}, {}}};
+        jacobi_batch(sp);
+        ctmk::spectrum_delta(st, sp[0].S.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
+        side_end();
+    }
+
     // ---- renormalised left edge (row-wise absorption, both neighbouring bonds)
     Tn X = ctr("xuosn,xlb->nuoslb", PbkB, K);
     X = ctr("nuoslb,plumd->nosbpmd", X, A);
@@ -1033,30 +1101,13 @@ void Worker::step(Net& N, int64_t chi)
     X = ctr("xaoqun,xlb->naoqulb", PibB, Bt);
     X = ctr("naoqulb,qlumt->naobmt", X, A);
     Tn Tb_n = ctr("naobmt,kbaot->nmk", X, PbkT);
-    // ---- corners: second-stage projectors on the stage-1 renormalised corners
-    Tn W1 = ctr("cdfqre,Xqre->cdfX", C1p, P4T);
-    Tn C1_n = mat(ctr("cdfX,Ycdf->XY", W1, P4T));
-    Tn W4 = ctr("cwhXyi,cwhx->xXyi", C4p, P4B);
-    Tn C4_n = mat(ctr("xXyi,Xyiz->xz", W4, P4B));
     Tk_n = mat(Tk_n);
     Ti_n = mat(Ti_n);
     Tb_n = mat(Tb_n);
-    ctmk::symmetrize(st, C1_n.p, (int)k4);
-    ctmk::symmetrize(st, C4_n.p, (int)k4);
-    normalize(C1_n);
-    normalize(C4_n);
     normalize(Tk_n);
     normalize(Ti_n);
     normalize(Tb_n);
-
-    // ---- convergence spectrum of C1 C2 C3 C4 = (C1 C4)^2 (FP64 in every form)
-    Prec spec64(*this, CTM_FP64);
-    Tn R1 = ctr("ab,bc->ac", C1_n, C4_n);
-    Tn R = mat(ctr("ab,bc->ac", R1, R1));
-    ctmk::trace(st, R.p, (int)k4, N.sc + 7);
-    std::vector<JReq> sp{JReq{R.p, k4, k4, false, {}, {}, {}}};
-    jacobi_batch(sp);
-    ctmk::spectrum_delta(st, sp[0].S.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
+    side_wait();
 
     // ---- store
     N.xbk = k4;
