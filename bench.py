@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-from synth_inputs import WORKLOADS, workload_peps  # noqa: E402
+from synth_inputs import WORKLOADS, raw_peps, workload_peps  # noqa: E402
 
 PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
@@ -59,13 +59,44 @@ def measured_traffic(cls):
     return data["kernels"][TRAFFIC_KEY[cls]]["hbm_bytes_per_launch"]
 
 
-def gpu_eval(ctm, torch, w, A, g, stream, profile=False, precision=0, refine=False):
+def gpu_eval(ctm, torch, w, A, g, stream, profile=False, precision=0, refine=False, method="split"):
     c = ctm.SplitCTM(w["beta"], A, w["chi"], max_iter=w["max_iter"], tol=w["tol"],
-                     stream=stream, profile=profile, precision=precision, refine=refine)
+                     stream=stream, profile=profile, precision=precision, refine=refine, method=method)
     done, delta, conv = c.iterate(0)
     f, lk3, lk2 = c.free_energy()
     c.grad(g)
     return c, dict(iters=done, delta=delta, converged=conv, f=f)
+
+
+def method_sweep(ctm, torch, steps, moves=20, skip=5):
+    """Split-CTMRG against the reduced method on the same kernels (the runtime
+    comparison of Sec. IV A): time per move of both networks for D = 2..6 at
+    chi = D^2 and at chi = 100, measured over `moves` moves after `skip`
+    untimed ones (moves to convergence depend on the tensor; per-move cost
+    does not), and f after those moves."""
+    beta = 0.22
+    for chi_rule in ("D^2", "100"):
+        for D in (2, 3, 4, 5, 6):
+            chi = D * D if chi_rule == "D^2" else 100
+            A = torch.from_numpy(raw_peps(D, 0)).cuda()
+            row = dict(D=D, chi=chi, beta=beta, moves_timed=moves)
+            for method in ("split", "reduced"):
+                best = None
+                for _ in range(max(1, steps)):
+                    c = ctm.SplitCTM(beta, A, chi, max_iter=skip + moves, tol=0.0, method=method)
+                    c.iterate(skip)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    c.iterate(moves)
+                    torch.cuda.synchronize()
+                    dt = (time.perf_counter() - t0) / moves
+                    best = dt if best is None else min(best, dt)
+                    f = c.free_energy()[0]
+                    _, nbytes = c.query()
+                    c.close()
+                row[method] = dict(ms_per_move=1e3 * best, f=f, device_bytes=int(nbytes))
+            row["split_over_reduced_time"] = row["split"]["ms_per_move"] / row["reduced"]["ms_per_move"]
+            print(json.dumps(row), flush=True)
 
 
 def cpu_baseline(name, sample_iters):
@@ -98,6 +129,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true")
+    ap.add_argument("--no-reduced-leg", action="store_true")
+    ap.add_argument("--method-sweep", action="store_true",
+                    help="only compare split-CTMRG with the reduced method: time per move for "
+                         "D = 2..6 at chi = D^2 and chi = 100 (one JSON line per case)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -118,6 +153,10 @@ def main():
 
     import torch
     from paper_2506_19339_amd import ctm
+
+    if args.method_sweep:
+        method_sweep(ctm, torch, args.steps)
+        return
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
@@ -195,6 +234,28 @@ def main():
                     rel_f_vs_fp64=abs(info32["f"] - info["f"]) / abs(info["f"]),
                     speedup_vs_fp64=(args.steps / el32) / evals_per_s)
 
+    reduced = None
+    if not args.no_reduced_leg:
+        # the reduced method (fused site tensors, C4v CTMRG) on the same
+        # workload and the same kernels: the paper's comparison method
+        print("reduced-method leg", file=sys.stderr, flush=True)
+        c, _ = gpu_eval(ctm, torch, w, A, g, sp, method="reduced")
+        c.close()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        itr = []
+        for i in range(args.steps):
+            c, infor = gpu_eval(ctm, torch, w, A, g, sp, method="reduced")
+            itr.append(infor["iters"])
+            c.close()
+        torch.cuda.synchronize()
+        elr = time.perf_counter() - t1
+        reduced = dict(evals_per_s=args.steps / elr, ms_per_step=1e3 * elr / args.steps,
+                       iters_per_eval=float(np.mean(itr)), ms_per_iter=1e3 * elr / float(np.sum(itr)),
+                       converged=bool(infor["converged"]), f=infor["f"],
+                       rel_f_vs_split=abs(infor["f"] - info["f"]) / abs(info["f"]),
+                       split_ms_per_iter=1e3 * elapsed / float(np.sum(iters)))
+
     cpu = None
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -230,6 +291,7 @@ def main():
         "f": info["f"],
         "roofline": roofline,
         "fp32_form": fp32,
+        "reduced_method": reduced,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CTM_ABI_VERSION 3
+#define CTM_ABI_VERSION 4
 
 typedef struct ctm_ctx ctm_ctx;
 
@@ -84,6 +84,17 @@ typedef enum {
 
 #define CTM_FLAG_DEVICE_PTRS 1
 #define CTM_FLAG_PROFILE 2      /* record HIP events around GEMM / Jacobi launches */
+/* CTM_FLAG_REDUCED: contract both networks with the reduced method instead of
+ * split-CTMRG (Sec. II; the comparison method of Sec. IV): the ket, PEPO and
+ * bra layers of a site are fused into one tensor a with bond D^2 d (norm
+ * network: D^2), and a C4v-symmetric CTMRG with one corner C (chi x chi) and
+ * one edge T (chi x D^2 d x chi) truncates the enlarged corner to the chi
+ * eigenvectors of largest |eigenvalue| (svd_cutoff relative to the largest).
+ * Convergence uses the singular values of C^4 / Tr C^4 (Sec. III D); f and g
+ * use the same estimators as the split path.  CTM_FP64 only (CTM_EINVAL
+ * otherwise).  Device memory grows as chi^2 (D^2 d)^2 for the enlarged
+ * corner and (D^2 d)^4 for a. */
+#define CTM_FLAG_REDUCED 4
 
 typedef struct {
     int D;              /* PEPS virtual bond dimension, 1 <= D <= 8               */

@@ -163,6 +163,11 @@ struct Net {
     double* sc = nullptr;            // scalars: n1 n2h n2v n0 | lk flag | tr
     double* E = nullptr;             // bra environment, 2 D^4
     double* sv = nullptr;            // spectrum buffer
+    // reduced method (CTM_FLAG_REDUCED): corner in C1, edge T [chi][Df][chi],
+    // fused site tensor a [Df]^4 with Df = D d D
+    int64_t Df = 0;
+    double* a = nullptr;
+    double* Tf = nullptr;
 };
 
 // per-kernel-class launch statistics (CTM_FLAG_PROFILE): HIP events on the
@@ -229,6 +234,7 @@ struct Worker {
     bool no_group = false;           // testing aid: one launch per product in mm_group
     bool trace_sweeps = false;       // testing aid: log the sweeps of every Jacobi job (profile mode)
     bool warm_starts = true;         // keep each slot's Ritz basis for the next move
+    bool reduced = false;            // reduced (unsplit) C4v CTMRG on the fused site tensor
     double last_delta = 1.0;         // spectrum change of this network's last move (host copy)
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
     double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
@@ -249,6 +255,11 @@ struct Worker {
         D = d_bond;
         A = a;
         profiling = (c.flags & CTM_FLAG_PROFILE) != 0;
+        reduced = (c.flags & CTM_FLAG_REDUCED) != 0;
+        // the reduced method's enlarged corner (chi D^2 d wide, cut in a flat
+        // part of its spectrum) needs the full power iteration every move: with
+        // two warm steps its spectrum change stalls near 1e-7 (D = 5, chi = 100)
+        if (reduced) warm_starts = false;
         HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
         HIPCHK(hipStreamCreateWithFlags(&st_side, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&ev_side_fork, hipEventDisableTiming));
@@ -946,6 +957,9 @@ struct Worker {
     // ---------------- one symmetric split-CTMRG iteration of one network
     void step(Net& N, int64_t chi);
     void values(Net& N, bool with_env);
+    // ---------------- the same for the reduced method
+    void step_reduced(Net& N, int64_t chi);
+    void values_reduced(Net& N, bool with_env);
 };
 
 // --------------------------------------------------------------------------
@@ -953,6 +967,10 @@ struct Worker {
 // --------------------------------------------------------------------------
 void Worker::step(Net& N, int64_t chi)
 {
+    if (reduced) {
+        step_reduced(N, chi);
+        return;
+    }
     Prec bulk_prec(*this, bulk);   // absorption, environments, projector application
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
@@ -1125,6 +1143,10 @@ void Worker::step(Net& N, int64_t chi)
 // with_env: also the bra environment into N.E and its overlap with A in N.sc[6]
 void Worker::values(Net& N, bool with_env)
 {
+    if (reduced) {
+        values_reduced(N, with_env);
+        return;
+    }
     Prec fp64(*this, CTM_FP64);   // f and g are evaluated in FP64 in every form
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
@@ -1173,6 +1195,98 @@ void Worker::values(Net& N, bool with_env)
         Tn Env = mat(ctr("qtnbwvsz,vntez->qwbse", G, BR));   // [q, Bl, Bu, Br, Bd]
         ctmk::copy(st, Env.p, N.E, Env.n());
         ctmk::dot(st, Env.p, this->A, Env.n(), N.sc + 6, part, 0);
+    }
+    ws.release(mk);
+}
+
+// ---------------------------------------------------------------------------
+// reduced method (Sec. II): C4v-symmetric CTMRG on the fused site tensor a,
+// one corner C (chi x chi, symmetric) and one edge T [chi][Df][chi]
+// (symmetric in its chi legs) for all four directions
+// ---------------------------------------------------------------------------
+void Worker::step_reduced(Net& N, int64_t chi)
+{
+    Prec fp64(*this, CTM_FP64);
+    const Arena::Mark mk = ws.mark();
+    const int64_t x = N.xbk, Df = N.Df, n = x * Df;
+    Tn C = make_tn(N.C1, {x, x});
+    Tn T = make_tn(N.Tf, {x, Df, x});
+    Tn a = make_tn(N.a, {Df, Df, Df, Df});
+    // enlarged corner M[(b,d),(c,r)] = C[x,y] T[x,m,b] T[y,n,c] a[m,n,r,d]
+    Tn X = ctr("xy,xmb->ymb", C, T);
+    X = ctr("ymb,ync->mbnc", X, T);
+    Tn M = view(mat(ctr("mbnc,mnrd->bdcr", X, a)), {n, n});
+    ctmk::symmetrize(st, M.p, (int)n);
+    // the chi eigenvectors of largest |lambda|: for the symmetric M these are
+    // its leading right singular vectors (singular values = |lambda|)
+    std::vector<SvdReq> rq(1);
+    rq[0].M = M;
+    rq[0].kk = std::min<int64_t>(chi, n);
+    rq[0].slot = 0;
+    svd_batch(rq);
+    const double cut = cfg.svd_cutoff > 0 ? cfg.svd_cutoff : kDefaultCutoff;
+    ctmk::count_above(st, rq[0].S.p, (int)rq[0].kk, cut, icount);
+    int rank = 0;
+    HIPCHK(hipMemcpyAsync(&rank, icount, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t k = std::max<int64_t>(1, std::min<int64_t>(rq[0].kk, rank));
+    Tn VT = rq[0].VT;                          // rows: the kept eigenvectors
+    VT.d[0] = k;
+    // C' = V^T M V
+    Tn Cn = mm(VT, false, mm(M, false, VT, true), false);
+    // T'[z,r,w] = V[(a,u),z] T[a,m,b] a[m,u,r,d] V[(b,d),w], the projector
+    // taken into the edge before the site (never forms T a)
+    Tn P3 = view(VT, {k, x, Df});
+    Tn Y = ctr("zau,amb->zumb", P3, T);
+    Y = ctr("zumb,murd->zbrd", Y, a);
+    Tn Tn_ = mat(ctr("zbrd,wbd->zrw", Y, P3));
+    ctmk::symmetrize(st, Cn.p, (int)k);
+    ctmk::symmetrize_edge(st, Tn_.p, (int)k, (int)Df);
+    normalize(Cn);
+    normalize(Tn_);
+    // convergence spectrum: singular values of C^4 / Tr C^4 (= lambda^4, normalised)
+    Tn R1 = ctr("ab,bc->ac", Cn, Cn);
+    Tn R = mat(ctr("ab,bc->ac", R1, R1));
+    ctmk::trace(st, R.p, (int)k, N.sc + 7);
+    std::vector<JReq> sp{JReq{R.p, k, k, false, {}, {}, {}}};
+    jacobi_batch(sp);
+    ctmk::spectrum_delta(st, sp[0].S.p, (int)k, N.sc + 7, N.s_old, N.n_old, N.delta);
+    N.xbk = k;
+    ctmk::copy(st, Cn.p, N.C1, Cn.n());
+    ctmk::copy(st, Tn_.p, N.Tf, Tn_.n());
+    ws.release(mk);
+}
+
+// n1 (3x3 patch), n2 (3x2 strip), n0 = Tr C^4; with_env: the bra environment
+// E[q,l,u,r,d] (the fused-site environment with the ket and PEPO contracted)
+// and its overlap with A
+void Worker::values_reduced(Net& N, bool with_env)
+{
+    Prec fp64(*this, CTM_FP64);
+    const Arena::Mark mk = ws.mark();
+    const int64_t x = N.xbk, Df = N.Df;
+    Tn C = make_tn(N.C1, {x, x});
+    Tn T = make_tn(N.Tf, {x, Df, x});
+    Tn a = make_tn(N.a, {Df, Df, Df, Df});
+    Tn CTC = ctr("xa,amb->xmb", C, T);
+    CTC = mat(ctr("xmb,by->xmy", CTC, C));              // corner-edge-corner row
+    Tn s2 = ctr("xmy,xmy->", CTC, CTC);
+    Tn R1 = ctr("ab,bc->ac", C, C);
+    Tn s0 = ctr("ab,ba->", R1, R1);
+    // environment of the centre site: top row with the left edge, bottom row
+    // with the right edge, joined over the two corner-edge bonds
+    Tn X1 = ctr("xuy,xlc->uylc", CTC, T);
+    Tn X2 = ctr("cde,yre->cdyr", CTC, T);
+    Tn env = mat(ctr("uylc,cdyr->lurd", X1, X2));
+    Tn s1 = ctr("lurd,lurd->", env, a);
+    ctmk::copy(st, s1.p, N.sc + 0, 1);
+    ctmk::copy(st, s2.p, N.sc + 1, 1);
+    ctmk::copy(st, s2.p, N.sc + 2, 1);
+    ctmk::copy(st, s0.p, N.sc + 3, 1);
+    ctmk::log_kappa(st, N.sc, N.sc + 4);
+    if (with_env) {
+        ctmk::unfuse_env(st, env.p, this->A, N.O, (int)D, (int)N.d, N.E);
+        ctmk::dot(st, N.E, this->A, 2 * D * D * D * D, N.sc + 6, part, 0);
     }
     ws.release(mk);
 }
@@ -1291,6 +1405,11 @@ static void init_net(ctm_ctx* c, Net& N, int d)
     N.sc = c->keep(16);
     N.E = c->keep(2 * D * D * D * D);
     N.sv = c->keep(x);
+    if (c->cfg.flags & CTM_FLAG_REDUCED) {
+        N.Df = D * d * D;
+        N.a = c->keep(N.Df * N.Df * N.Df * N.Df);
+        N.Tf = c->keep(x * x * N.Df);
+    }
 }
 
 static void reset_env(Worker& W, Net& N, int D)
@@ -1298,6 +1417,8 @@ static void reset_env(Worker& W, Net& N, int D)
     const int64_t d = N.d;
     N.xbk = N.xki = N.xib = 1;
     W.last_delta = 1.0;
+    if (W.reduced)   // product boundary of the fused legs: T[0, m, 0] = 1/sqrt(Df)
+        ctmk::fill(W.st, N.Tf, N.Df, 1.0 / std::sqrt((double)N.Df));
     ctmk::fill(W.st, N.C1, 1, 1.0);
     ctmk::fill(W.st, N.C4, 1, 1.0);
     ctmk::fill(W.st, N.Tk, D, 1.0 / std::sqrt((double)D));
@@ -1328,6 +1449,8 @@ static void load_tensor(ctm_ctx* c, double beta, const double* A)
     HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, W.st));
     ctmk::ising_pepo(W.st, c->net[0].O, beta);
     ctmk::identity_pepo(W.st, c->net[1].O);
+    if (c->cfg.flags & CTM_FLAG_REDUCED)
+        for (Net& N : c->net) ctmk::fuse_site(W.st, c->A, N.O, c->D, N.d, N.a);
     HIPCHK(hipStreamSynchronize(W.st));
     W.ws.release(mk);
     c->order(0, 1);
@@ -1488,6 +1611,10 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
         return CTM_EINVAL;
     }
     if (cfg->lp_tol < 0.0) { g_init_err = "lp_tol must be >= 0"; return CTM_EINVAL; }
+    if ((cfg->flags & CTM_FLAG_REDUCED) && cfg->precision != CTM_FP64) {
+        g_init_err = "the reduced method runs in CTM_FP64 only";
+        return CTM_EINVAL;
+    }
     ctm_ctx* c = new (std::nothrow) ctm_ctx();
     if (!c) { g_init_err = "host allocation failed"; return CTM_ENOMEM; }
     ctm_status s = guarded(c, [&] {

@@ -83,6 +83,11 @@ void randn(hipStream_t s, double* x, int64_t n, uint64_t seed);
 void d4_project(hipStream_t s, const double* A, double* out, int D);
 void ising_pepo(hipStream_t s, double* O, double beta);
 void identity_pepo(hipStream_t s, double* O);
+// reduced method: fused site tensor (Df = D dd D per leg), bra environment
+// from the fused-site environment, chi-leg symmetrisation of an edge tensor
+void fuse_site(hipStream_t s, const double* A, const double* O, int D, int dd, double* a);
+void unfuse_env(hipStream_t s, const double* env, const double* A, const double* O, int D, int dd, double* E);
+void symmetrize_edge(hipStream_t s, double* T, int x, int Df);
 void log_kappa(hipStream_t s, const double* sc, double* out);
 void free_energy(hipStream_t s, const double* lk3, const double* lk2, double beta, double* f);
 void grad_combine(hipStream_t s, const double* E3, const double* n13, const double* E2,

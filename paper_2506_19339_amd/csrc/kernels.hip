@@ -748,6 +748,116 @@ void symmetrize(hipStream_t s, double* x, int n)
     hipLaunchKernelGGL(symmetrize_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, x, n);
 }
 
+// T[a][m][b] and T[b][m][a] replaced by their mean (edge tensor of the
+// reduced method, symmetric in its two chi legs)
+__global__ void symmetrize_edge_kernel(double* T, int x, int Df)
+{
+    const int64_t n = (int64_t)x * x * Df;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i % x), m = (int)((i / x) % Df), a = (int)(i / ((int64_t)x * Df));
+        if (a < b) {
+            const int64_t j = ((int64_t)b * Df + m) * x + a;
+            const double v = 0.5 * (T[i] + T[j]);
+            T[i] = v;
+            T[j] = v;
+        }
+    }
+}
+
+void symmetrize_edge(hipStream_t s, double* T, int x, int Df)
+{
+    hipLaunchKernelGGL(symmetrize_edge_kernel, dim3(grid_for((int64_t)x * x * Df)), dim3(256), 0, s, T, x, Df);
+}
+
+// Fused site tensor of the reduced method (Sec. II):
+// a[(lk,li,lb),(uk,ui,ub),(rk,ri,rb),(dk,di,db)] = sum_{p,q} A[p,lk,uk,rk,dk]
+// O[p,q,li,ui,ri,di] A[q,lb,ub,rb,db]; fused leg (ket, PEPO, bra) with the
+// bra index fastest.  With the identity PEPO (dd = 1) this is the norm
+// network's sum_p A[p] A[p].
+__global__ void fuse_site_kernel(const double* __restrict__ A, const double* __restrict__ O, int D, int dd,
+                                 double* __restrict__ a)
+{
+    const int Df = D * dd * D;
+    const int64_t n = (int64_t)Df * Df * Df * Df;
+    const int64_t D4 = (int64_t)D * D * D * D;
+    const int d4 = dd * dd * dd * dd;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t t = e;
+        int k[4], o[4], b[4];
+        for (int leg = 3; leg >= 0; --leg) {
+            int f = (int)(t % Df);
+            t /= Df;
+            b[leg] = f % D;
+            f /= D;
+            o[leg] = f % dd;
+            k[leg] = f / dd;
+        }
+        const int64_t ik = (((int64_t)k[0] * D + k[1]) * D + k[2]) * D + k[3];
+        const int64_t ib = (((int64_t)b[0] * D + b[1]) * D + b[2]) * D + b[3];
+        const int io = ((o[0] * dd + o[1]) * dd + o[2]) * dd + o[3];
+        double v = 0.0;
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) v += A[p * D4 + ik] * O[(p * 2 + q) * d4 + io] * A[q * D4 + ib];
+        a[e] = v;
+    }
+}
+
+void fuse_site(hipStream_t s, const double* A, const double* O, int D, int dd, double* a)
+{
+    const int64_t Df = (int64_t)D * dd * D;
+    hipLaunchKernelGGL(fuse_site_kernel, dim3(grid_for(Df * Df * Df * Df)), dim3(256), 0, s, A, O, D, dd, a);
+}
+
+// Environment of the bra tensor from the environment env of the fused site
+// (legs as in fuse_site):
+// E[q,lb,ub,rb,db] = sum env[...] A[p,lk,uk,rk,dk] O[p,q,li,ui,ri,di] over
+// p and the ket and PEPO indices.  One workgroup per output entry, fixed
+// reduction tree.
+__global__ void unfuse_env_kernel(const double* __restrict__ env, const double* __restrict__ A,
+                                  const double* __restrict__ O, int D, int dd, double* __restrict__ E)
+{
+    __shared__ double sh[16];
+    const int64_t D4 = (int64_t)D * D * D * D;
+    const int d4 = dd * dd * dd * dd;
+    const int Df = D * dd * D;
+    const int64_t out = blockIdx.x;                 // q * D4 + ib
+    const int q = (int)(out / D4);
+    int64_t ib = out % D4;
+    int b[4];
+    for (int leg = 3; leg >= 0; --leg) {
+        b[leg] = (int)(ib % D);
+        ib /= D;
+    }
+    const int64_t terms = 2 * D4 * d4;
+    double v = 0.0;
+    for (int64_t t = threadIdx.x; t < terms; t += blockDim.x) {
+        const int io = (int)(t % d4);
+        const int64_t ik = (t / d4) % D4;
+        const int p = (int)(t / (d4 * D4));
+        int64_t r = ik;
+        int k[4], o[4];
+        int rr = io;
+        for (int leg = 3; leg >= 0; --leg) {
+            k[leg] = (int)(r % D);
+            r /= D;
+            o[leg] = rr % dd;
+            rr /= dd;
+        }
+        int64_t fe = 0;
+        for (int leg = 0; leg < 4; ++leg) fe = fe * Df + ((int64_t)k[leg] * dd + o[leg]) * D + b[leg];
+        v += env[fe] * A[p * D4 + ik] * O[(p * 2 + q) * d4 + io];
+    }
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) E[out] = v;
+}
+
+void unfuse_env(hipStream_t s, const double* env, const double* A, const double* O, int D, int dd, double* E)
+{
+    const int64_t n = 2 * (int64_t)D * D * D * D;
+    hipLaunchKernelGGL(unfuse_env_kernel, dim3((unsigned)n), dim3(256), 0, s, env, A, O, D, dd, E);
+}
+
 // rows (mode 0) or columns (mode 1) of a row-major R x C matrix scaled by f[i]
 __global__ void scale_lines_kernel(double* x, int R, int Cc, const double* __restrict__ f, int mode)
 {

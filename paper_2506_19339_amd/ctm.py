@@ -16,6 +16,7 @@ LIB_NAME = "libctm.so"
 CTM_FP64, CTM_FP32, CTM_BF16 = 0, 1, 2
 CTM_FLAG_DEVICE_PTRS = 1
 CTM_FLAG_PROFILE = 2
+CTM_FLAG_REDUCED = 4
 
 STATUS = {0: "CTM_OK", 1: "CTM_EINVAL", 2: "CTM_ENOMEM", 3: "CTM_EDEVICE",
           4: "CTM_ENOCONV", 5: "CTM_ENUMERIC", 6: "CTM_ESTATE"}
@@ -102,18 +103,24 @@ class SplitCTM:
 
     ``A`` is a float64 array of shape (2, D, D, D, D) ([p][l][u][r][d]); a torch
     tensor on the GPU is passed by device pointer.  ``stream`` is a HIP stream
-    handle (int) or None for the default stream.
+    handle (int) or None for the default stream.  ``method="reduced"`` contracts
+    both networks with the reduced (fused-site, C4v) CTMRG instead of
+    split-CTMRG (CTM_FLAG_REDUCED; FP64 only).
     """
 
     def __init__(self, beta, A, chi, max_iter=100, tol=0.0, precision=CTM_FP64,
                  power_iters=0, svd_cutoff=0.0, stream=None, lib=None, profile=False,
-                 lp_tol=0.0, refine=False):
+                 lp_tol=0.0, refine=False, method="split"):
+        if method not in ("split", "reduced"):
+            raise ValueError("method must be 'split' or 'reduced'")
         self._lib = lib or load_library()
         self._ctx = ctypes.c_void_p()
         D = int(np.shape(A)[1])
         flags, ptr, keep = self._tensor_arg(A)
         if profile:
             flags |= CTM_FLAG_PROFILE
+        if method == "reduced":
+            flags |= CTM_FLAG_REDUCED
         cfg = _Config(D, int(chi), int(max_iter), float(tol), int(precision), flags,
                       int(power_iters), float(svd_cutoff), float(lp_tol), int(bool(refine)))
         st = self._lib.ctm_init(ctypes.byref(cfg), float(beta), ptr,
