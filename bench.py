@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true")
     ap.add_argument("--no-reduced-leg", action="store_true")
+    ap.add_argument("--no-lbfgs-leg", action="store_true")
+    ap.add_argument("--lbfgs-steps", type=int, default=5)
     ap.add_argument("--method-sweep", action="store_true",
                     help="only compare split-CTMRG with the reduced method: time per move for "
                          "D = 2..6 at chi = D^2 and chi = 100 (one JSON line per case)")
@@ -256,6 +258,22 @@ def main():
                        rel_f_vs_split=abs(infor["f"] - info["f"]) / abs(info["f"]),
                        split_ms_per_iter=1e3 * elapsed / float(np.sum(iters)))
 
+    lbfgs = None
+    if not args.no_lbfgs_leg:
+        # the step after the hot path: L-BFGS on f from the workload tensor,
+        # every evaluation warm-started from the last converged environments
+        from paper_2506_19339_amd import optimize
+        print("lbfgs leg", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        with optimize.Optimizer(w["beta"], workload_peps(args.workload), w["chi"], env_tol=w["tol"],
+                                env_max_iter=w["max_iter"]) as opt:
+            r = opt.run(max_steps=args.lbfgs_steps, gtol=1e-7)
+        dt = time.perf_counter() - t1
+        lbfgs = dict(steps=r.steps, evaluations=r.evaluations, evals_per_s=r.evaluations / dt,
+                     moves_per_eval=r.moves / r.evaluations, cold_moves=r.history[0][3],
+                     f_start=r.history[0][1], f_end=r.f, g_inf_start=r.history[0][2], g_inf_end=r.g_inf)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -292,6 +310,7 @@ def main():
         "roofline": roofline,
         "fp32_form": fp32,
         "reduced_method": reduced,
+        "lbfgs": lbfgs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -7,13 +7,17 @@ set to the library's relative cutoff (1e-8) so that both keep the same ranks.
 Eigenvectors are fixed only up to sign (and rotations within degenerate
 eigenspaces), so only gauge-invariant results are compared: f, ln kappa of
 each network, the corner spectrum and the gradient."""
+import os
+
 import numpy as np
 import pytest
 import torch
 
 from oracle import exact, model, unsplit
 from paper_2506_19339_amd import ctm
-from synth_inputs import raw_peps
+from synth_inputs import WORKLOADS, raw_peps, workload_peps
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -128,6 +132,26 @@ def test_reduced_gradient_central_differences():
                 fs.append(c.free_energy()[0])
         fd = (fs[0] - fs[1]) / (2 * h)
         assert abs(fd - np.sum(g * v)) <= 1e-5 * abs(fd), (fd, np.sum(g * v))
+
+
+def test_reduced_d5_chi100_vs_stored_oracle():
+    """The bench workload (beta = 0.22, D = 5, chi = 100: enlarged corners of
+    5000 x 5000 and 2500 x 2500) after 12 reduced steps against the oracle's
+    exact-eigh reduced method, stored by tests/golden/make_reference.py."""
+    path = os.path.join(GOLDEN, "d5_chi100_reduced_it12.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle reference not generated")
+    ref = np.load(path)
+    w = WORKLOADS["d5_chi100"]
+    A = torch.from_numpy(workload_peps("d5_chi100")).cuda()
+    with ctm.SplitCTM(w["beta"], A, w["chi"], svd_cutoff=float(ref["eig_cutoff"]), method="reduced") as c:
+        assert c.iterate(int(ref["n_iter"]))[0] == int(ref["n_iter"])
+        f, l3, l2 = c.free_energy()
+        s3 = c.spectrum(3)
+    assert abs(l3 - float(ref["log_kappa3"])) <= 1e-10 * abs(float(ref["log_kappa3"]))
+    assert abs(l2 - float(ref["log_kappa2"])) <= 1e-10 * abs(float(ref["log_kappa2"]))
+    assert abs(f - float(ref["f"])) <= 1e-9 * abs(float(ref["f"])), (f, float(ref["f"]))
+    assert _close_spectra(s3, ref["spectrum3"], 1e-9)
 
 
 def test_reduced_rejects_reduced_precision():
