@@ -1495,6 +1495,7 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
     __shared__ int rnk[kRegJacobi + 1];
     __shared__ double gsum[NP];
     __shared__ int rotated;
+    __shared__ unsigned int maxr;                  // largest (gamma^2 / alpha beta) of the sweep, float bits
     __shared__ double fro2;
     const JacobiJob jb = jobs.job[blockIdx.x];
     const int m = jb.m, n = jb.n;
@@ -1553,7 +1554,10 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             c = 1.0 / sqrt(1.0 + t * t);
             sn = c * t;
-            if (l16 == 0) rotated = 1;
+            if (l16 == 0) {
+                rotated = 1;
+                atomicMax(&maxr, __float_as_uint((float)(ga * ga / (al * be))));
+            }
         }
 #pragma unroll
         for (int u = 0; u < RL; ++u) {
@@ -1594,7 +1598,10 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
     // (2p+1), right = a (2p+2); then the column at 2p+2 leaves and the one at
     // 2p arrives into a, restoring the even-step roles.
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (tid == 0) rotated = 0;
+        if (tid == 0) {
+            rotated = 0;
+            maxr = 0u;
+        }
         __syncthreads();
         for (int step = 0; step < ne; step += 2) {
             rotate(ax, bx, av, bv, ia, ib, false);
@@ -1631,7 +1638,10 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             }
             __syncthreads();
         }
-        if (rotated == 0) {
+        // done when no pair rotated, or when every rotation of this sweep was
+        // below 1e-10 (then the pairs are orthogonal to ~1e-20 after it, below
+        // the rotation threshold, and a further sweep would rotate nothing)
+        if (rotated == 0 || __uint_as_float(maxr) < 1e-20f) {
             if (jb.sweeps && tid == 0) jb.sweeps[0] = sweep + 1;
             break;
         }
