@@ -217,9 +217,10 @@ struct Worker {
     int D = 0;
     const double* A = nullptr;       // D4-projected A, owned by the context
     hipStream_t st = nullptr;        // created by the context (default priority)
-    hipStream_t st_side = nullptr;   // side stream of the convergence spectrum (default priority)
+    hipStream_t st_side = nullptr;   // side work (convergence spectrum): the caller's stream
     hipEvent_t ev_side_fork = nullptr, ev_side_done = nullptr;
     bool on_side = false, side_pending = false;
+    bool side_ok = true;             // side work allowed in this call (one context at a time)
     Arena ws;
     std::vector<void*> owned;        // persistent allocations of this worker
     double* part = nullptr;          // reduction partials
@@ -261,7 +262,6 @@ struct Worker {
         // two warm steps its spectrum change stalls near 1e-7 (D = 5, chi = 100)
         if (reduced) warm_starts = false;
         HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        HIPCHK(hipStreamCreateWithFlags(&st_side, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&ev_side_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&ev_side_done, hipEventDisableTiming));
         part = keep(ctmk::kRedBlocks);
@@ -286,10 +286,6 @@ struct Worker {
         }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         ev_pool.clear();
-        if (st_side) {
-            (void)hipStreamSynchronize(st_side);
-            (void)hipStreamDestroy(st_side);
-        }
         if (ev_side_fork) (void)hipEventDestroy(ev_side_fork);
         if (ev_side_done) (void)hipEventDestroy(ev_side_done);
         st_side = nullptr;
@@ -301,12 +297,15 @@ struct Worker {
     // Work enqueued between side_begin and side_end goes to the side stream
     // (after everything enqueued on the worker stream so far) and runs
     // concurrently with what the worker stream does next, until side_wait.
-    // The side work must not use the split-K workspace or the reduction
-    // scratch of the worker stream.  In profile mode everything stays on the
-    // worker stream.
+    // The side stream is the caller's stream, idle between the fork and the
+    // join of a call, so that a context uses three streams in all (a process
+    // gets four hardware queues by default; two more streams would share
+    // queues with the worker streams and serialise with them).  The side work
+    // must not use the split-K workspace or the reduction scratch of the
+    // worker stream.  In profile mode everything stays on the worker stream.
     void side_begin()
     {
-        if (profiling) return;
+        if (profiling || !side_ok) return;
         HIPCHK(hipEventRecord(ev_side_fork, st));
         HIPCHK(hipStreamWaitEvent(st_side, ev_side_fork, 0));
         std::swap(st, st_side);
@@ -1481,6 +1480,9 @@ static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done,
     std::vector<int> st(n, CTM_OK);
     for (int i = 0; i < n; ++i) {
         ctm_ctx* c = cs[i];
+        // contexts advanced together may share the caller's stream: their side
+        // work would queue up behind each other there, so it stays inline
+        for (auto& x : c->w) x.side_ok = (n == 1);
         const int left = std::max(0, c->cfg.max_iter - (c->iters - c->base_iters));
         budget[i] = n_iter > 0 ? n_iter : (n_iter == 0 ? left : std::min(left, -n_iter));
         capped[i] = until && budget[i] == left;   // the budget ends at max_iter
@@ -1627,6 +1629,7 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
         c->A = c->keep(2 * (int64_t)c->D * c->D * c->D * c->D);
         for (auto& x : c->w) {
             x.setup(*cfg, c->D, c->A);
+            x.st_side = c->ust;
             if (const char* e = std::getenv("CTM_JACOBI_EXACT_MAX")) {   // testing aid
                 x.exact_min = std::atoll(e);
                 x.exact_area = x.exact_min * x.exact_min * 4;
