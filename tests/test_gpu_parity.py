@@ -69,9 +69,12 @@ def test_first_move_is_exact_growth():
     compare(gpu_run(0.2, A, 16, 1), oracle_run(0.2, A, 16, 1))
 
 
-@pytest.mark.parametrize("D,chi,n_iter,seed", [(3, 20, 30, 1), (2, 7, 40, 4)])
+@pytest.mark.parametrize("D,chi,n_iter,seed", [(3, 20, 30, 1), (2, 7, 40, 4), (1, 4, 20, 0), (2, 1, 10, 0),
+                                              (2, 2, 15, 0), (4, 9, 10, 2)])
 def test_other_shapes(D, chi, n_iter, seed):
-    """Ragged chi (not a multiple of the GEMM tile) and D = 3."""
+    """Ragged chi (not a multiple of the GEMM tile), D = 3 and D = 4, and the
+    degenerate cases: D = 1 (product states, every virtual bond of size one),
+    chi = 1 (every environment bond truncated to one) and chi = 2."""
     A = raw_peps(D, seed)
     compare(gpu_run(0.22, A, chi, n_iter), oracle_run(0.22, A, chi, n_iter))
 
