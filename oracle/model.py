@@ -53,6 +53,17 @@ def pepo_O(beta):
     return ein("sp,sq,sl,su,sr,sd->pqlurd", s, s, s, s, s, s)
 
 
+def pepo_Oz(beta):
+    """Impurity PEPO of the spin at a site: O with the spin's value under the
+    sum, Oz[p,q,l,u,r,d] = sum_s sigma(s) sW[s,p] sW[s,q] sW[s,l] sW[s,u]
+    sW[s,r] sW[s,d] with sigma = +1 for s = 0 and -1 for s = 1 (the local
+    observable of Sec. IV B as an impurity tensor).  In the converged
+    triple-layer environment <sigma> = n1(Oz) / n1(O)."""
+    s = sqrt_W(beta)
+    sig = np.array([1.0, -1.0])
+    return ein("s,sp,sq,sl,su,sr,sd->pqlurd", sig, s, s, s, s, s, s)
+
+
 def identity_pepo():
     """PEPO of the norm network <psi|psi>: delta_{pq} with in-plane legs of size 1.
 

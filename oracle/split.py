@@ -479,6 +479,18 @@ def log_kappa(env, A, O):
     return float(np.log(kap)), n1
 
 
+def magnetization(env, A, beta):
+    """<sigma> at a site of the PEPO layer: the 3x3 patch with the impurity
+    PEPO at its centre over the same patch with O, both in the converged
+    triple-layer environment env."""
+    bot = bottom_row(env)
+    vals = []
+    for O in (model.pepo_Oz(beta), model.pepo_O(beta)):
+        _, _, up_bk = upper_sequence(env, A, O)
+        vals.append(ein("wetgz,wgtez->", up_bk, bot))
+    return float(vals[0] / vals[1])
+
+
 def bra_environment(env, A, O):
     """d n1 / d B[q, l, u, r, d]: the 3x3 patch with the bra tensor removed."""
     _, up_ib, _ = upper_sequence(env, A, O)                     # [tib,q,Od,Ad,Bu,rib]

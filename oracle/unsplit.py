@@ -136,6 +136,16 @@ def site_environment(C, T):
     return ein("lurce,cde->lurd", X, CTC)             # bottom row closes
 
 
+def magnetization(C, T, A, beta):
+    """<sigma> at a site: the fused site tensor built with the impurity PEPO,
+    over the one built with O, in the 3x3 patch of the converged triple-layer
+    environment (C, T)."""
+    env = site_environment(C, T)
+    nz = ein("lurd,lurd->", env, model.fuse_triple(A, model.pepo_Oz(beta)))
+    n1 = ein("lurd,lurd->", env, model.fuse_triple(A, model.pepo_O(beta)))
+    return float(nz / n1)
+
+
 def log_kappa(C, T, a):
     n1, n2, n0 = patch_values(C, T, a)
     kap = n1 * n0 / (n2 * n2)

@@ -96,6 +96,42 @@ def test_ctm_core_reproduces_onsager(beta):
 
 # ------------------------------------------------------ reduced (unsplit) CTM
 
+@pytest.mark.parametrize("n", [1, 2])
+def test_magnetization_untruncated_split_equals_unsplit(n):
+    """The impurity contraction of the split patch and of the fused-site patch
+    are independent codes for the same finite network when nothing is
+    truncated: the two magnetisations agree."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 1))
+    O = model.pepo_O(beta)
+    env, _, _, _ = split.run(A, O, 10 ** 9, n)
+    C, T, _, _ = unsplit.run(model.fuse_triple(A, O), (2, 2, 2), 10 ** 9, n)
+    ms, mu = split.magnetization(env, A, beta), unsplit.magnetization(C, T, A, beta)
+    assert abs(ms) > 1e-3
+    assert abs(ms - mu) < 1e-12
+
+
+def test_magnetization_spin_flip_and_symmetric_state():
+    """Z2: flipping the physical index of A (A[p] -> A[1 - p]) maps the network
+    with O to itself and Oz to -Oz, so m changes sign; the flip-symmetric product
+    state (1, 1)/sqrt(2) has m = 0; |m| <= 1."""
+    beta, chi = 0.2, 12
+    A = model.d4_symmetrize(raw_peps(2, 1))
+    O = model.pepo_O(beta)
+    for B, want in ((A, None), (A[::-1].copy(), "flip")):
+        env, _, _, _ = split.run(B, O, chi, 40)
+        C, T, _, _ = unsplit.run(model.fuse_triple(B, O), (2, 2, 2), chi, 40)
+        m = (split.magnetization(env, B, beta), unsplit.magnetization(C, T, B, beta))
+        if want is None:
+            m0 = m
+        else:
+            assert abs(m[0] + m0[0]) < 1e-10 and abs(m[1] + m0[1]) < 1e-10
+    assert 1e-3 < abs(m0[1]) <= 1.0
+    P = model.embed_product_state(2, +1)
+    env, _, _, _ = split.run(P, O, chi, 20)
+    assert abs(split.magnetization(env, P, beta)) < 1e-13
+
+
 @pytest.mark.parametrize("sign", [+1, -1])
 @pytest.mark.parametrize("D", [2, 3])
 def test_unsplit_product_state_closed_form(sign, D):
