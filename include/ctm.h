@@ -167,6 +167,15 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A);
 /* Iterations done so far, and the device bytes the context holds. */
 ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes);
 
+/* Magnetisation <sigma> of a spin of the PEPO layer (Sec. IV B: local
+ * observables as impurity tensors in the converged environment): the 3x3
+ * patch of the triple-layer network with the centre PEPO replaced by the
+ * impurity PEPO Oz (the spin's value +1 / -1 for s = 0 / 1 under the sum over
+ * s), divided by the same patch with O.  Both methods (split and reduced).
+ * *m receives the host double.  CTM_ESTATE before any iteration,
+ * CTM_ENUMERIC when the patch value is zero or non-finite. */
+ctm_status ctm_magnetization(ctm_ctx* c, double* m);
+
 /* Launch statistics of a context built with CTM_FLAG_PROFILE: which = 0 the
  * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernels, 2 the Cholesky QR kernels,
  * 3 the FP32 / BF16 MFMA GEMM kernel, 4 the split-K reduction of the GEMMs.

@@ -959,6 +959,9 @@ struct Worker {
     // ---------------- the same for the reduced method
     void step_reduced(Net& N, int64_t chi);
     void values_reduced(Net& N, bool with_env);
+    // n1 of the 3x3 patch with the PEPO Oc at its centre (the rest of the
+    // network as in N) into *out (device scalar)
+    void centre_value(Net& N, const double* Oc, double* out);
 };
 
 // --------------------------------------------------------------------------
@@ -1287,6 +1290,55 @@ void Worker::values_reduced(Net& N, bool with_env)
         ctmk::unfuse_env(st, env.p, this->A, N.O, (int)D, (int)N.d, N.E);
         ctmk::dot(st, N.E, this->A, 2 * D * D * D * D, N.sc + 6, part, 0);
     }
+    ws.release(mk);
+}
+
+void Worker::centre_value(Net& N, const double* Oc, double* out)
+{
+    Prec fp64(*this, CTM_FP64);
+    const Arena::Mark mk = ws.mark();
+    const int64_t D = this->D, d = N.d, P = 2;
+    Tn A = make_tn(const_cast<double*>(this->A), {P, D, D, D, D});
+    Tn O = make_tn(const_cast<double*>(Oc), {P, P, d, d, d, d});
+    if (reduced) {
+        const int64_t x = N.xbk, Df = N.Df;
+        Tn C = make_tn(N.C1, {x, x});
+        Tn T = make_tn(N.Tf, {x, Df, x});
+        Tn a = tmp({Df, Df, Df, Df});
+        ctmk::fuse_site(st, this->A, Oc, (int)D, (int)d, a.p);
+        Tn CTC = ctr("xa,amb->xmb", C, T);
+        CTC = mat(ctr("xmb,by->xmy", CTC, C));
+        Tn X1 = ctr("xuy,xlc->uylc", CTC, T);
+        Tn X2 = ctr("cde,yre->cdyr", CTC, T);
+        Tn env = mat(ctr("uylc,cdyr->lurd", X1, X2));
+        Tn s1 = ctr("lurd,lurd->", env, a);
+        ctmk::copy(st, s1.p, out, 1);
+        ws.release(mk);
+        return;
+    }
+    // split: the upper two rows with the centre site, closed by the bottom
+    // row (the n1 contraction of values() with the centre PEPO replaced)
+    Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
+    Tn K = make_tn(N.Tk, {N.xbk, D, N.xki});
+    Tn I = make_tn(N.Ti, {N.xki, d, N.xib});
+    Tn Bt = make_tn(N.Tb, {N.xib, D, N.xbk});
+    Tn Rk = perm(Bt, "bma->amb"), Ri = perm(I, "bma->amb"), Rb = perm(K, "bma->amb");
+    Tn H = ctr("xy,xkc->ykc", C1, K);
+    H = ctr("ykc,cie->ykie", H, I);
+    H = ctr("ykie,ebf->ykibf", H, Bt);
+    Tn TR = ctr("ykibf,fz->ykibz", H, C4);
+    Tn BR = perm(TR, "fecba->abcef");
+    Tn U = ctr("ykibz,ylg->glkibz", TR, K);
+    U = ctr("glkibz,plkrn->gpnribz", U, A);
+    U = ctr("gpnribz,zrh->gpnibh", U, Rk);
+    U = ctr("gpnibh,gmj->jmpnibh", U, I);
+    U = ctr("jmpnibh,pqmist->jqtsnbh", U, O);
+    U = ctr("jqtsnbh,hsk->jqtnbk", U, Ri);
+    U = ctr("jqtnbk,jwv->vwqtnbk", U, Bt);
+    U = ctr("vwqtnbk,qwbse->vsetnk", U, A);
+    Tn upbk = ctr("vsetnk,ksz->vetnz", U, Rb);
+    Tn s1 = ctr("vetnz,vntez->", upbk, BR);
+    ctmk::copy(st, s1.p, out, 1);
     ws.release(mk);
 }
 
@@ -1732,6 +1784,31 @@ ctm_status ctm_grad(ctm_ctx* c, double* g)
         W.ws.release(mk);
         c->join();
     });
+}
+
+ctm_status ctm_magnetization(ctm_ctx* c, double* m)
+{
+    if (!c || !m) return CTM_EINVAL;
+    if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
+    double h[2] = {0.0, 0.0};
+    ctm_status s = guarded(c, [&] {
+        c->fork();
+        Worker& W = c->w[0];
+        const Arena::Mark mk = W.ws.mark();
+        double* Oz = W.ws.alloc(64);
+        double* val = W.ws.alloc(2);
+        ctmk::ising_pepo(W.st, Oz, c->beta, true);
+        W.centre_value(c->net[0], Oz, val + 0);
+        W.centre_value(c->net[0], c->net[0].O, val + 1);
+        HIPCHK(hipMemcpyAsync(h, val, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
+        HIPCHK(hipStreamSynchronize(W.st));
+        W.ws.release(mk);
+        c->join();
+        if (!(h[1] != 0.0) || !std::isfinite(h[0] / h[1]))
+            throw CtmError(CTM_ENUMERIC, "zero or non-finite network value");
+    });
+    if (s == CTM_OK) *m = h[0] / h[1];
+    return s;
 }
 
 ctm_status ctm_corner_spectrum(ctm_ctx* c, int which, double* s, int cap, int* n)

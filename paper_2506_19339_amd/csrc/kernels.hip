@@ -980,7 +980,9 @@ void d4_project(hipStream_t s, const double* A, double* out, int D)
 // O[p,q,l,u,r,d] = sum_s w[s,p] w[s,q] w[s,l] w[s,u] w[s,r] w[s,d], w = sqrt(W),
 // W = [[e^b, e^-b], [e^-b, e^b]]: eigenvalues 2cosh b (vector (1,1)/sqrt2) and
 // 2sinh b (vector (1,-1)/sqrt2), so w = (sqrt(2cosh b) P+ + sqrt(2sinh b) P-).
-__global__ void ising_pepo_kernel(double* O, double beta)
+// impurity = 1: the spin's value sigma(s) = +1 (s = 0), -1 (s = 1) under the
+// sum (impurity tensor of the local magnetisation)
+__global__ void ising_pepo_kernel(double* O, double beta, int impurity)
 {
     const int i = threadIdx.x;
     if (i >= 64) return;
@@ -991,16 +993,16 @@ __global__ void ising_pepo_kernel(double* O, double beta)
     for (int k = 5; k >= 0; --k) { idx[k] = rem & 1; rem >>= 1; }
     double acc = 0.0;
     for (int s = 0; s < 2; ++s) {
-        double t = 1.0;
+        double t = (impurity && s == 1) ? -1.0 : 1.0;
         for (int k = 0; k < 6; ++k) t *= w[s][idx[k]];
         acc += t;
     }
     O[i] = acc;
 }
 
-void ising_pepo(hipStream_t s, double* O, double beta)
+void ising_pepo(hipStream_t s, double* O, double beta, bool impurity)
 {
-    hipLaunchKernelGGL(ising_pepo_kernel, dim3(1), dim3(64), 0, s, O, beta);
+    hipLaunchKernelGGL(ising_pepo_kernel, dim3(1), dim3(64), 0, s, O, beta, impurity ? 1 : 0);
 }
 
 __global__ void identity_pepo_kernel(double* O)

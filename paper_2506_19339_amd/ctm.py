@@ -20,7 +20,7 @@ CTM_FLAG_REDUCED = 4
 
 STATUS = {0: "CTM_OK", 1: "CTM_EINVAL", 2: "CTM_ENOMEM", 3: "CTM_EDEVICE",
           4: "CTM_ENOCONV", 5: "CTM_ENUMERIC", 6: "CTM_ESTATE"}
-CTM_ENOCONV = 4
+CTM_OK, CTM_EINVAL, CTM_ENOMEM, CTM_EDEVICE, CTM_ENOCONV, CTM_ENUMERIC, CTM_ESTATE = range(7)
 
 
 class CtmError(RuntimeError):
@@ -69,6 +69,7 @@ def load_library(path=None):
                                       ctypes.POINTER(ctypes.c_int)]
     lib.ctm_free_energy.argtypes = [vp, dp, dp, dp]
     lib.ctm_grad.argtypes = [vp, vp]
+    lib.ctm_magnetization.argtypes = [vp, dp]
     lib.ctm_corner_spectrum.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.ctm_reset_tensor.argtypes = [vp, ctypes.c_double, vp]
     lib.ctm_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong)]
@@ -170,6 +171,12 @@ class SplitCTM:
         self._check(self._lib.ctm_grad(self._ctx, g.ctypes.data_as(ctypes.c_void_p)))
         assert g.size == n
         return g
+
+    def magnetization(self):
+        """<sigma> of a PEPO-layer spin in the converged triple-layer environment."""
+        m = ctypes.c_double()
+        self._check(self._lib.ctm_magnetization(self._ctx, ctypes.byref(m)))
+        return m.value
 
     def spectrum(self, which=3):
         cap = 4096
