@@ -82,67 +82,80 @@ class Optimizer:
         return np.inf, None, 0
 
     def run(self, max_steps=100, gtol=1e-7, c1=1e-4, callback=None):
-        x = self.A.copy()
-        f, g, mv = self.f_and_grad(x)
-        if g is None:
-            raise ctm.CtmError(ctm.CTM_ENUMERIC, "no positive network value at the start")
-        S, Y = [], []
-        hist = [(0, f, float(np.max(np.abs(g))), mv)]
-        step = 0
-        while step < max_steps and np.max(np.abs(g)) >= gtol:
-            # two-loop recursion: d = -H g
-            q = g.copy()
-            al = []
-            for s, y in zip(reversed(S), reversed(Y)):
-                rho = 1.0 / np.sum(y * s)
-                a = rho * np.sum(s * q)
-                q -= a * y
-                al.append((rho, a, s, y))
-            if S:
-                q *= np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * Y[-1])
-            else:
-                q *= 1e-2 / max(np.linalg.norm(g), 1e-300)   # first step: 1e-2 of |A| = 1
-            for rho, a, s, y in reversed(al):
-                b = rho * np.sum(y * q)
-                q += (a - b) * s
-            d = -q
-            slope = np.sum(g * d)
-            if slope >= 0.0:           # not a descent direction: restart from steepest descent
-                S, Y = [], []
-                d = -g * (1e-2 / max(np.linalg.norm(g), 1e-300))
-                slope = np.sum(g * d)
-            t = 1.0
-            while True:
-                xn = x + t * d
-                fn, gn, mv = self.f_and_grad(xn)
-                if gn is not None and fn <= f + c1 * t * slope:
-                    break
-                t *= 0.5
-                if t < 1e-10:
-                    return self._result(x, f, g, step, False, hist)
-            # rescale to unit norm (f and the direction of g are unchanged;
-            # g scales with 1 / |A|)
-            nrm = np.linalg.norm(xn)
-            xn = xn / nrm
-            gn = gn * nrm
-            s, y = xn - x, gn - g
-            if np.sum(s * y) > 1e-12 * np.linalg.norm(s) * np.linalg.norm(y):
-                S.append(s)
-                Y.append(y)
-                if len(S) > self.m:
-                    S.pop(0)
-                    Y.pop(0)
-            x, f, g = xn, fn, gn
-            step += 1
-            hist.append((step, f, float(np.max(np.abs(g))), mv))
-            if callback:
-                callback(step, f, g)
-        return self._result(x, f, g, step, bool(np.max(np.abs(g)) < gtol), hist)
+        r = lbfgs(self.f_and_grad, self.A, max_steps=max_steps, gtol=gtol, history=self.m, c1=c1,
+                  callback=callback)
+        self.A = r.A
+        r.evaluations, r.moves = self.evaluations, self.moves
+        return r
 
-    def _result(self, x, f, g, step, conv, hist):
-        self.A = x
-        return OptResult(A=x, f=f, g_inf=float(np.max(np.abs(g))), steps=step, evaluations=self.evaluations,
-                         moves=self.moves, converged=conv, history=hist)
+
+
+def lbfgs(fg, x0, max_steps=100, gtol=1e-7, history=10, c1=1e-4, first_step=1e-2, callback=None):
+    """Minimise a scale-invariant function with L-BFGS.
+
+    fg(x) -> (f, g, cost) with g the gradient (None and f = +inf where f is not
+    defined); f(c x) = f(x) is assumed, so every accepted point is rescaled to
+    unit norm (and g by the norm).  The first step has length first_step.
+    Returns an OptResult (evaluations and moves are filled in by the caller)."""
+    x = np.asarray(x0, dtype=np.float64)
+    x = x / np.linalg.norm(x)
+    f, g, cost = fg(x)
+    if g is None:
+        raise ctm.CtmError(ctm.CTM_ENUMERIC, "the objective is not defined at the start")
+    S, Y = [], []
+    hist = [(0, f, float(np.max(np.abs(g))), cost)]
+    step = 0
+    while step < max_steps and np.max(np.abs(g)) >= gtol:
+        # two-loop recursion: d = -H g
+        q = g.copy()
+        al = []
+        for s, y in zip(reversed(S), reversed(Y)):
+            rho = 1.0 / np.sum(y * s)
+            a = rho * np.sum(s * q)
+            q -= a * y
+            al.append((rho, a, s, y))
+        if S:
+            q *= np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * Y[-1])
+        else:
+            q *= first_step / max(np.linalg.norm(g), 1e-300)
+        for rho, a, s, y in reversed(al):
+            b = rho * np.sum(y * q)
+            q += (a - b) * s
+        d = -q
+        slope = np.sum(g * d)
+        if slope >= 0.0:           # not a descent direction: restart from steepest descent
+            S, Y = [], []
+            d = -g * (first_step / max(np.linalg.norm(g), 1e-300))
+            slope = np.sum(g * d)
+        t = 1.0
+        while True:
+            xn = x + t * d
+            fn, gn, cost = fg(xn)
+            if gn is not None and fn <= f + c1 * t * slope:
+                break
+            t *= 0.5
+            if t < 1e-10:
+                return OptResult(A=x, f=f, g_inf=float(np.max(np.abs(g))), steps=step, evaluations=0,
+                                 moves=0, converged=False, history=hist)
+        # rescale to unit norm (f and the direction of g are unchanged; g
+        # scales with 1 / |x|)
+        nrm = np.linalg.norm(xn)
+        xn = xn / nrm
+        gn = gn * nrm
+        s, y = xn - x, gn - g
+        if np.sum(s * y) > 1e-12 * np.linalg.norm(s) * np.linalg.norm(y):
+            S.append(s)
+            Y.append(y)
+            if len(S) > history:
+                S.pop(0)
+                Y.pop(0)
+        x, f, g = xn, fn, gn
+        step += 1
+        hist.append((step, f, float(np.max(np.abs(g))), cost))
+        if callback:
+            callback(step, f, g)
+    return OptResult(A=x, f=f, g_inf=float(np.max(np.abs(g))), steps=step, evaluations=0, moves=0,
+                     converged=bool(np.max(np.abs(g)) < gtol), history=hist)
 
 
 def minimize(beta, A0, chi, max_steps=100, gtol=1e-7, **kw):
