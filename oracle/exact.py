@@ -15,7 +15,7 @@ independent facts the CTMRG oracles are checked against.
   * Central finite differences of a scalar function along given directions.
 """
 import numpy as np
-from scipy import integrate
+from scipy import integrate, special
 
 
 def onsager_log_kappa(beta):
@@ -38,6 +38,16 @@ def onsager_log_kappa_double(beta):
         lambda t2, t1: np.log(c2 - s2 * (np.cos(t1) + np.cos(t2))),
         0.0, np.pi, 0.0, np.pi, epsabs=1e-13, epsrel=1e-13)
     return float(np.log(2.0) + 4.0 * I / (8.0 * np.pi ** 2))
+
+
+def onsager_nn_correlation(beta):
+    """Nearest-neighbour <s s'> of the 2D square-lattice Ising model (J = 1):
+    (1/2) coth(2b) [1 + (2/pi)(2 tanh^2(2b) - 1) K(k)], k = 2 sinh 2b / cosh^2 2b,
+    K the complete elliptic integral of the first kind (Onsager's internal
+    energy per site, -2 <s s'>)."""
+    k = 2.0 * np.sinh(2 * beta) / np.cosh(2 * beta) ** 2
+    K = special.ellipk(k * k)
+    return float(0.5 / np.tanh(2 * beta) * (1.0 + (2.0 / np.pi) * (2.0 * np.tanh(2 * beta) ** 2 - 1.0) * K))
 
 
 def product_state_f(beta, sign=+1):

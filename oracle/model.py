@@ -116,6 +116,13 @@ def fuse_double(A):
     return a2.reshape(D * D, D * D, D * D, D * D)
 
 
+def ising_2d_site_z(beta):
+    """The 2D site tensor with the spin's value (+1 / -1 for s = 0 / 1) under the
+    sum: the impurity of the 2D pins."""
+    s = sqrt_W(beta)
+    return ein("s,sl,su,sr,sd->lurd", np.array([1.0, -1.0]), s, s, s, s)
+
+
 def ising_2d_site(beta):
     """Square-lattice 2D Ising site tensor a[l,u,r,d] = sum_s prod_4 sqrt(W)[s,.]
     (the 2D analogue of O, used only to pin the CTMRG core against Onsager)."""

@@ -146,6 +146,40 @@ def magnetization(C, T, A, beta):
     return float(nz / n1)
 
 
+def two_site_value(C, T, a1, a2):
+    """The 3 x 4 patch: corners and edges around two horizontally adjacent sites
+    a1 (left) and a2 (right), sharing the bond k (a1's right leg, a2's left leg):
+      C[x,a] T[a,m,b] T[b,n,c] C[c,y]          (top row)
+      T[x,l,p] a1[l,m,k,d] a2[k,n,r,e] T[y,r,q] (middle row)
+      C[p,z] T[z,d,g] T[g,e,h] C[h,q]          (bottom row)
+    summed as the left half L[b,k,g] times the right half R[b,k,g]."""
+    L = ein("xa,amb->xmb", C, T)
+    L = ein("xmb,xlp->mblp", L, T)
+    L = ein("mblp,lmkd->bpkd", L, a1)
+    L = ein("bpkd,pz->bkdz", L, C)
+    L = ein("bkdz,zdg->bkg", L, T)
+    R = ein("bnc,cy->bny", T, C)
+    R = ein("bny,yrq->bnrq", R, T)
+    R = ein("bnrq,knre->bkqe", R, a2)
+    R = ein("bkqe,hq->bkeh", R, C)
+    R = ein("bkeh,geh->bkg", R, T)
+    return float(ein("bkg,bkg->", L, R))
+
+
+def nn_correlation(C, T, a, az):
+    """<s s'> of two horizontally adjacent spins carried by the site tensors:
+    the two-site patch with both impurity tensors az over the one with a."""
+    return two_site_value(C, T, az, az) / two_site_value(C, T, a, a)
+
+
+def bond_correlation(C, T, A, beta):
+    """In-plane nearest-neighbour <sigma sigma'> of the PEPO layer in the
+    converged triple-layer environment (C, T)."""
+    a = model.fuse_triple(A, model.pepo_O(beta))
+    az = model.fuse_triple(A, model.pepo_Oz(beta))
+    return nn_correlation(C, T, a, az)
+
+
 def log_kappa(C, T, a):
     n1, n2, n0 = patch_values(C, T, a)
     kap = n1 * n0 / (n2 * n2)

@@ -94,6 +94,35 @@ def test_ctm_core_reproduces_onsager(beta):
     assert abs(lk - exact.onsager_log_kappa(beta)) < 1e-12
 
 
+@pytest.mark.parametrize("beta", [0.2, 0.3, 0.6])
+def test_onsager_nn_correlation_is_the_energy_derivative(beta):
+    """<s s'> = (1/2) d ln kappa_2D / d beta (two bonds per site): the elliptic
+    closed form against central differences of the quadrature form."""
+    h = 1e-5
+    fd = (exact.onsager_log_kappa(beta + h) - exact.onsager_log_kappa(beta - h)) / (4 * h)
+    assert abs(exact.onsager_nn_correlation(beta) - fd) < 1e-8
+
+
+@pytest.mark.parametrize("beta", [0.2, 0.3])
+def test_ctm_core_reproduces_onsager_nn_correlation(beta):
+    """The two-site impurity patch in the converged 2D environment gives the
+    exact nearest-neighbour correlation."""
+    a, az = model.ising_2d_site(beta), model.ising_2d_site_z(beta)
+    C, T, _, _ = unsplit.run(a, (2,), 32, 400, tol=1e-14)
+    assert abs(unsplit.nn_correlation(C, T, a, az) - exact.onsager_nn_correlation(beta)) < 1e-11
+
+
+def test_product_state_bond_correlation_is_the_2d_one():
+    """For A = (1, 1)/sqrt(2) the triple-layer network is cosh(beta) times the 2D
+    Ising network per site, with or without the impurity PEPOs, so the in-plane
+    <sigma sigma'> is the 2D nearest-neighbour correlation."""
+    beta = 0.2
+    A = model.embed_product_state(2, +1)
+    O = model.pepo_O(beta)
+    C, T, _, _ = unsplit.run(model.fuse_triple(A, O), (2, 2, 2), 24, 400, tol=1e-14)
+    assert abs(unsplit.bond_correlation(C, T, A, beta) - exact.onsager_nn_correlation(beta)) < 1e-11
+
+
 # ------------------------------------------------------ reduced (unsplit) CTM
 
 @pytest.mark.parametrize("n", [1, 2])
