@@ -176,6 +176,16 @@ ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes
  * CTM_ENUMERIC when the patch value is zero or non-finite. */
 ctm_status ctm_magnetization(ctm_ctx* c, double* m);
 
+/* In-plane nearest-neighbour correlation <sigma sigma'> of two PEPO-layer
+ * spins (the bond energy of Sec. IV B, -J <sigma sigma'> per in-plane bond):
+ * the 3x4 patch of the triple-layer network around two horizontally adjacent
+ * sites, both with the impurity PEPO Oz, divided by the same patch with O.
+ * Contexts built with CTM_FLAG_REDUCED only (CTM_EINVAL otherwise: the split
+ * path has no two-site patch).  *zz receives the host double.  CTM_ESTATE
+ * before any iteration, CTM_ENUMERIC when the patch value is zero or
+ * non-finite. */
+ctm_status ctm_bond_correlation(ctm_ctx* c, double* zz);
+
 /* Launch statistics of a context built with CTM_FLAG_PROFILE: which = 0 the
  * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernels, 2 the Cholesky QR kernels,
  * 3 the FP32 / BF16 MFMA GEMM kernel, 4 the split-K reduction of the GEMMs.

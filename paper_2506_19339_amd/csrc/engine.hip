@@ -962,6 +962,9 @@ struct Worker {
     // n1 of the 3x3 patch with the PEPO Oc at its centre (the rest of the
     // network as in N) into *out (device scalar)
     void centre_value(Net& N, const double* Oc, double* out);
+    // reduced method: the 3x4 patch around two horizontally adjacent sites,
+    // both with the PEPO Oc, into *out (device scalar)
+    void pair_value(Net& N, const double* Oc, double* out);
 };
 
 // --------------------------------------------------------------------------
@@ -1339,6 +1342,32 @@ void Worker::centre_value(Net& N, const double* Oc, double* out)
     Tn upbk = ctr("vsetnk,ksz->vetnz", U, Rb);
     Tn s1 = ctr("vetnz,vntez->", upbk, BR);
     ctmk::copy(st, s1.p, out, 1);
+    ws.release(mk);
+}
+
+void Worker::pair_value(Net& N, const double* Oc, double* out)
+{
+    Prec fp64(*this, CTM_FP64);
+    const Arena::Mark mk = ws.mark();
+    const int64_t x = N.xbk, Df = N.Df;
+    Tn C = make_tn(N.C1, {x, x});
+    Tn T = make_tn(N.Tf, {x, Df, x});
+    Tn a = tmp({Df, Df, Df, Df});
+    ctmk::fuse_site(st, this->A, Oc, (int)D, (int)N.d, a.p);
+    // left half L[b,k,g]: top-left corner and edge, left edge, site 1,
+    // bottom-left corner and edge; right half R[b,k,g] likewise
+    Tn L = ctr("xa,amb->xmb", C, T);
+    L = ctr("xmb,xlp->mblp", L, T);
+    L = ctr("mblp,lmkd->bpkd", L, a);
+    L = ctr("bpkd,pz->bkdz", L, C);
+    L = mat(ctr("bkdz,zdg->bkg", L, T));
+    Tn R = ctr("bnc,cy->bny", T, C);
+    R = ctr("bny,yrq->bnrq", R, T);
+    R = ctr("bnrq,knre->bkqe", R, a);
+    R = ctr("bkqe,hq->bkeh", R, C);
+    R = mat(ctr("bkeh,geh->bkg", R, T));
+    Tn v = ctr("bkg,bkg->", L, R);
+    ctmk::copy(st, v.p, out, 1);
     ws.release(mk);
 }
 
@@ -1808,6 +1837,35 @@ ctm_status ctm_magnetization(ctm_ctx* c, double* m)
             throw CtmError(CTM_ENUMERIC, "zero or non-finite network value");
     });
     if (s == CTM_OK) *m = h[0] / h[1];
+    return s;
+}
+
+ctm_status ctm_bond_correlation(ctm_ctx* c, double* zz)
+{
+    if (!c || !zz) return CTM_EINVAL;
+    if (!(c->cfg.flags & CTM_FLAG_REDUCED)) {
+        c->err = "the two-site patch is built for the reduced method (CTM_FLAG_REDUCED) only";
+        return CTM_EINVAL;
+    }
+    if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
+    double h[2] = {0.0, 0.0};
+    ctm_status s = guarded(c, [&] {
+        c->fork();
+        Worker& W = c->w[0];
+        const Arena::Mark mk = W.ws.mark();
+        double* Oz = W.ws.alloc(64);
+        double* val = W.ws.alloc(2);
+        ctmk::ising_pepo(W.st, Oz, c->beta, true);
+        W.pair_value(c->net[0], Oz, val + 0);
+        W.pair_value(c->net[0], c->net[0].O, val + 1);
+        HIPCHK(hipMemcpyAsync(h, val, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
+        HIPCHK(hipStreamSynchronize(W.st));
+        W.ws.release(mk);
+        c->join();
+        if (!(h[1] != 0.0) || !std::isfinite(h[0] / h[1]))
+            throw CtmError(CTM_ENUMERIC, "zero or non-finite network value");
+    });
+    if (s == CTM_OK) *zz = h[0] / h[1];
     return s;
 }
 

@@ -70,6 +70,7 @@ def load_library(path=None):
     lib.ctm_free_energy.argtypes = [vp, dp, dp, dp]
     lib.ctm_grad.argtypes = [vp, vp]
     lib.ctm_magnetization.argtypes = [vp, dp]
+    lib.ctm_bond_correlation.argtypes = [vp, dp]
     lib.ctm_corner_spectrum.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.ctm_reset_tensor.argtypes = [vp, ctypes.c_double, vp]
     lib.ctm_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong)]
@@ -177,6 +178,12 @@ class SplitCTM:
         m = ctypes.c_double()
         self._check(self._lib.ctm_magnetization(self._ctx, ctypes.byref(m)))
         return m.value
+
+    def bond_correlation(self):
+        """In-plane nearest-neighbour <sigma sigma'> (reduced-method contexts)."""
+        zz = ctypes.c_double()
+        self._check(self._lib.ctm_bond_correlation(self._ctx, ctypes.byref(zz)))
+        return zz.value
 
     def spectrum(self, which=3):
         cap = 4096

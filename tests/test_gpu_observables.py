@@ -1,11 +1,12 @@
-"""Site magnetisation from the impurity PEPO in the converged triple-layer
-environment (ctm_magnetization), split and reduced method, against the oracle
-(oracle.split.magnetization / oracle.unsplit.magnetization) on the same inputs,
-and against the spin-flip symmetry."""
+"""Impurity observables in the converged triple-layer environment: the site
+magnetisation (ctm_magnetization, split and reduced method) and the in-plane
+nearest-neighbour correlation (ctm_bond_correlation, reduced method), against
+the oracle on the same inputs, the spin-flip symmetry and, for the symmetric
+product state, Onsager's nearest-neighbour correlation."""
 import numpy as np
 import pytest
 
-from oracle import model, split, unsplit
+from oracle import exact, model, split, unsplit
 from paper_2506_19339_amd import ctm
 from synth_inputs import raw_peps
 
@@ -60,3 +61,35 @@ def test_magnetisation_before_iterating_is_a_state_error():
         with pytest.raises(ctm.CtmError) as e:
             c.magnetization()
         assert e.value.status == ctm.CTM_ESTATE
+
+
+@pytest.mark.parametrize("beta,D,chi,n,seed", [(0.2, 2, 12, 20, 1), (0.22, 3, 20, 15, 2)])
+def test_bond_correlation_vs_oracle(beta, D, chi, n, seed):
+    A = raw_peps(D, seed)
+    with ctm.SplitCTM(beta, A, chi, svd_cutoff=CUT, method="reduced") as c:
+        assert c.iterate(n)[0] == n
+        zz = c.bond_correlation()
+    As = model.d4_symmetrize(A)
+    O = model.pepo_O(beta)
+    C, T, _, _ = unsplit.run(model.fuse_triple(As, O), (D, 2, D), chi, n)
+    zo = unsplit.bond_correlation(C, T, As, beta)
+    assert abs(zz - zo) <= 1e-10, (zz, zo)
+
+
+def test_bond_correlation_of_the_product_state_is_onsagers():
+    """A = (1, 1)/sqrt(2): the triple-layer network is the 2D Ising network up to
+    a constant per site, so <sigma sigma'> is the 2D nearest-neighbour value."""
+    beta = 0.2
+    with ctm.SplitCTM(beta, model.embed_product_state(2, +1), 24, max_iter=400, tol=1e-13, svd_cutoff=CUT,
+                      method="reduced") as c:
+        assert c.iterate(0)[2]
+        zz = c.bond_correlation()
+    assert abs(zz - exact.onsager_nn_correlation(beta)) <= 1e-10, (zz, exact.onsager_nn_correlation(beta))
+
+
+def test_bond_correlation_needs_the_reduced_method():
+    with ctm.SplitCTM(0.2, raw_peps(2, 0), 8) as c:
+        c.iterate(2)
+        with pytest.raises(ctm.CtmError) as e:
+            c.bond_correlation()
+        assert e.value.status == ctm.CTM_EINVAL
