@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--no-reduced-leg", action="store_true")
     ap.add_argument("--no-lbfgs-leg", action="store_true")
     ap.add_argument("--lbfgs-steps", type=int, default=5)
+    ap.add_argument("--reduced-only", action="store_true",
+                    help="only time the reduced method on the workload (for profiling it alone)")
     ap.add_argument("--method-sweep", action="store_true",
                     help="only compare split-CTMRG with the reduced method: time per move for "
                          "D = 2..6 at chi = D^2 and chi = 100 (one JSON line per case)")
@@ -158,6 +160,23 @@ def main():
 
     if args.method_sweep:
         method_sweep(ctm, torch, args.steps)
+        return
+    if args.reduced_only:
+        w = WORKLOADS[args.workload]
+        A = torch.from_numpy(workload_peps(args.workload)).cuda()
+        g = torch.empty_like(A)
+        for i in range(args.warmup):
+            c, _ = gpu_eval(ctm, torch, w, A, g, None, method="reduced")
+            c.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            c, info = gpu_eval(ctm, torch, w, A, g, None, method="reduced")
+            c.close()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(args.steps, 1)
+        print(json.dumps(dict(method="reduced", workload=args.workload, s_per_eval=dt, iters=info["iters"],
+                              f=info["f"])), flush=True)
         return
 
     w = WORKLOADS[args.workload]
@@ -257,6 +276,14 @@ def main():
                        converged=bool(infor["converged"]), f=infor["f"],
                        rel_f_vs_split=abs(infor["f"] - info["f"]) / abs(info["f"]),
                        split_ms_per_iter=1e3 * elapsed / float(np.sum(iters)))
+        if not args.no_profile_pass:
+            # its GEMM class against the FP64 peak, as for the split path
+            c, _ = gpu_eval(ctm, torch, w, A, g, sp, profile=True, method="reduced")
+            n_l, kms, kfl, _ = c.kernel_stats(0)
+            c.close()
+            ach = kfl / (kms / 1e3) / 1e12 if kms > 0 else None
+            reduced["gemm"] = dict(launches=n_l, avg_launch_us=1e3 * kms / max(n_l, 1), achieved=ach,
+                                   peak=78.6, unit="TFLOP/s", frac=(ach / 78.6) if ach else None)
 
     lbfgs = None
     if not args.no_lbfgs_leg:
