@@ -491,6 +491,56 @@ def magnetization(env, A, beta):
     return float(vals[0] / vals[1])
 
 
+def two_site_value(env, A, O1, O2):
+    """The 3 x 4 patch around two horizontally adjacent sites with the PEPOs O1
+    (left) and O2 (right): the two-column top row, then the ket, PEPO and bra
+    layers of both sites absorbed layer by layer between the left edge chain
+    and its D2 image on the right, closed by the two-column bottom row."""
+    C1, C4, Tk, Ti, Tb = env["C1"], env["C4"], env["Tk"], env["Ti"], env["Tb"]
+    Rk, Ri, Rb = right_edge(env)
+    B = B_of(A)
+    # top row C1 - (Tk Ti Tb) - (Tk Ti Tb) - C2: [y, a o b (site 1 up), c p d (site 2 up), z]
+    X = ein("xy,xas->yas", C1, Tk)
+    X = ein("yas,sot->yaot", X, Ti)
+    X = ein("yaot,tbu->yaobu", X, Tb)
+    X = ein("yaobu,ucv->yaobcv", X, Tk)
+    X = ein("yaobcv,vpw->yaobcpw", X, Ti)
+    X = ein("yaobcpw,wdz->yaobcpdz", X, Tb)
+    X = ein("yaobcpdz,zq->yaobcpdq", X, C4)
+    # ket layer: left edge, A (site 1), A (site 2), right edge
+    X = ein("yaobcpdz,ylg->glaobcpdz", X, Tk)
+    X = ein("glaobcpdz,slare->gserobcpdz", X, A)
+    X = ein("gserobcpdz,trcvf->gseobtfvpdz", X, A)
+    X = ein("gseobtfvpdz,zvh->gseobtfpdh", X, Rk)
+    # PEPO layer
+    X = ein("gseobtfpdh,gmj->jmseobtfpdh", X, Ti)
+    X = ein("jmseobtfpdh,sqmonk->jqknebtfpdh", X, O1)
+    X = ein("jqknebtfpdh,twnpxu->jqkebwuxfdh", X, O2)
+    X = ein("jqkebwuxfdh,hxi->jqkebwufdi", X, Ri)
+    # bra layer
+    X = ein("jqkebwufdi,jLJ->JLqkebwufdi", X, Tb)
+    X = ein("JLqkebwufdi,qLbRE->JERkewufdi", X, B)
+    X = ein("JERkewufdi,wRdVF->JEkeFVufi", X, B)
+    up2 = ein("JEkeFVufi,iVH->JEkeFufH", X, Rb)               # [tbb, Bd1, Od1, Ad1, Bd2, Od2, Ad2, rbb]
+    # bottom row C4 - (Rk Ri Rb) - (Rk Ri Rb) - C3: [x4, Ad1 Od1 Bd1, Ad2 Od2 Bd2, x3]
+    Y = ein("xy,yas->xas", C4, Rk)
+    Y = ein("xas,sot->xaot", Y, Ri)
+    Y = ein("xaot,tbu->xaobu", Y, Rb)
+    Y = ein("xaobu,ucv->xaobcv", Y, Rk)
+    Y = ein("xaobcv,vpw->xaobcpw", Y, Ri)
+    Y = ein("xaobcpw,wdz->xaobcpdz", Y, Rb)
+    bot2 = ein("xaobcpdz,qz->xaobcpdq", Y, C1)
+    return float(ein("JEkeFufH,JekEfuFH->", up2, bot2))
+
+
+def bond_correlation(env, A, beta):
+    """In-plane nearest-neighbour <sigma sigma'> of the PEPO layer: the two-site
+    patch with both impurity PEPOs over the one with O, in the converged
+    triple-layer environment."""
+    O, Oz = model.pepo_O(beta), model.pepo_Oz(beta)
+    return two_site_value(env, A, Oz, Oz) / two_site_value(env, A, O, O)
+
+
 def bra_environment(env, A, O):
     """d n1 / d B[q, l, u, r, d]: the 3x3 patch with the bra tensor removed."""
     _, up_ib, _ = upper_sequence(env, A, O)                     # [tib,q,Od,Ad,Bu,rib]

@@ -140,6 +140,26 @@ def test_magnetization_untruncated_split_equals_unsplit(n):
     assert abs(ms - mu) < 1e-12
 
 
+@pytest.mark.parametrize("n", [1, 2])
+def test_bond_correlation_untruncated_split_equals_unsplit(n):
+    """The split two-site patch (two columns absorbed layer by layer) and the
+    fused-site two-site patch are independent codes for the same finite network
+    when nothing is truncated."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 1))
+    O = model.pepo_O(beta)
+    env, _, _, _ = split.run(A, O, 10 ** 9, n)
+    C, T, _, _ = unsplit.run(model.fuse_triple(A, O), (2, 2, 2), 10 ** 9, n)
+    assert abs(split.bond_correlation(env, A, beta) - unsplit.bond_correlation(C, T, A, beta)) < 1e-12
+
+
+def test_split_product_state_bond_correlation_is_onsagers():
+    beta = 0.2
+    P = model.embed_product_state(2, +1)
+    env, _, _, _ = split.run(P, model.pepo_O(beta), 16, 300, tol=1e-13)
+    assert abs(split.bond_correlation(env, P, beta) - exact.onsager_nn_correlation(beta)) < 1e-10
+
+
 def test_magnetization_spin_flip_and_symmetric_state():
     """Z2: flipping the physical index of A (A[p] -> A[1 - p]) maps the network
     with O to itself and Oz to -Oz, so m changes sign; the flip-symmetric product
