@@ -180,8 +180,9 @@ ctm_status ctm_magnetization(ctm_ctx* c, double* m);
  * spins (the bond energy of Sec. IV B, -J <sigma sigma'> per in-plane bond):
  * the 3x4 patch of the triple-layer network around two horizontally adjacent
  * sites, both with the impurity PEPO Oz, divided by the same patch with O.
- * Contexts built with CTM_FLAG_REDUCED only (CTM_EINVAL otherwise: the split
- * path has no two-site patch).  *zz receives the host double.  CTM_ESTATE
+ * Both methods (split: two edge columns and two sites absorbed layer by layer;
+ * reduced: left and right half of the fused-site patch).  *zz receives the
+ * host double.  CTM_ESTATE
  * before any iteration, CTM_ENUMERIC when the patch value is zero or
  * non-finite. */
 ctm_status ctm_bond_correlation(ctm_ctx* c, double* zz);

@@ -962,9 +962,10 @@ struct Worker {
     // n1 of the 3x3 patch with the PEPO Oc at its centre (the rest of the
     // network as in N) into *out (device scalar)
     void centre_value(Net& N, const double* Oc, double* out);
-    // reduced method: the 3x4 patch around two horizontally adjacent sites,
-    // both with the PEPO Oc, into *out (device scalar)
+    // the 3x4 patch around two horizontally adjacent sites, both with the
+    // PEPO Oc, into *out (device scalar)
     void pair_value(Net& N, const double* Oc, double* out);
+    void pair_value_split(Net& N, const double* Oc, double* out);
 };
 
 // --------------------------------------------------------------------------
@@ -1348,6 +1349,10 @@ void Worker::centre_value(Net& N, const double* Oc, double* out)
 void Worker::pair_value(Net& N, const double* Oc, double* out)
 {
     Prec fp64(*this, CTM_FP64);
+    if (!reduced) {
+        pair_value_split(N, Oc, out);
+        return;
+    }
     const Arena::Mark mk = ws.mark();
     const int64_t x = N.xbk, Df = N.Df;
     Tn C = make_tn(N.C1, {x, x});
@@ -1367,6 +1372,56 @@ void Worker::pair_value(Net& N, const double* Oc, double* out)
     R = ctr("bkqe,hq->bkeh", R, C);
     R = mat(ctr("bkeh,geh->bkg", R, T));
     Tn v = ctr("bkg,bkg->", L, R);
+    ctmk::copy(st, v.p, out, 1);
+    ws.release(mk);
+}
+
+// split environment: two-column top row, then the ket, PEPO and bra layers of
+// both sites absorbed layer by layer between the left edge chain and its D2
+// image, closed by the two-column bottom row
+void Worker::pair_value_split(Net& N, const double* Oc, double* out)
+{
+    const Arena::Mark mk = ws.mark();
+    const int64_t D = this->D, d = N.d, P = 2;
+    Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
+    Tn K = make_tn(N.Tk, {N.xbk, D, N.xki});
+    Tn I = make_tn(N.Ti, {N.xki, d, N.xib});
+    Tn Bt = make_tn(N.Tb, {N.xib, D, N.xbk});
+    Tn A = make_tn(const_cast<double*>(this->A), {P, D, D, D, D});
+    Tn O = make_tn(const_cast<double*>(Oc), {P, P, d, d, d, d});
+    Tn Rk = perm(Bt, "bma->amb"), Ri = perm(I, "bma->amb"), Rb = perm(K, "bma->amb");
+    // top row: [y, a o b (site 1 up), c p d (site 2 up), z]
+    Tn X = ctr("xy,xas->yas", C1, K);
+    X = ctr("yas,sot->yaot", X, I);
+    X = ctr("yaot,tbu->yaobu", X, Bt);
+    X = ctr("yaobu,ucv->yaobcv", X, K);
+    X = ctr("yaobcv,vpw->yaobcpw", X, I);
+    X = ctr("yaobcpw,wdz->yaobcpdz", X, Bt);
+    X = ctr("yaobcpdz,zq->yaobcpdq", X, C4);
+    // ket layer
+    X = ctr("yaobcpdz,ylg->glaobcpdz", X, K);
+    X = ctr("glaobcpdz,slare->gserobcpdz", X, A);
+    X = ctr("gserobcpdz,trcvf->gseobtfvpdz", X, A);
+    X = ctr("gseobtfvpdz,zvh->gseobtfpdh", X, Rk);
+    // PEPO layer
+    X = ctr("gseobtfpdh,gmj->jmseobtfpdh", X, I);
+    X = ctr("jmseobtfpdh,sqmonk->jqknebtfpdh", X, O);
+    X = ctr("jqknebtfpdh,twnpxu->jqkebwuxfdh", X, O);
+    X = ctr("jqkebwuxfdh,hxi->jqkebwufdi", X, Ri);
+    // bra layer
+    X = ctr("jqkebwufdi,jLJ->JLqkebwufdi", X, Bt);
+    X = ctr("JLqkebwufdi,qLbRE->JERkewufdi", X, A);
+    X = ctr("JERkewufdi,wRdVF->JEkeFVufi", X, A);
+    Tn up2 = ctr("JEkeFVufi,iVH->JEkeFufH", X, Rb);
+    // bottom row: [x4, Ad1 Od1 Bd1, Ad2 Od2 Bd2, x3]
+    Tn Y = ctr("xy,yas->xas", C4, Rk);
+    Y = ctr("xas,sot->xaot", Y, Ri);
+    Y = ctr("xaot,tbu->xaobu", Y, Rb);
+    Y = ctr("xaobu,ucv->xaobcv", Y, Rk);
+    Y = ctr("xaobcv,vpw->xaobcpw", Y, Ri);
+    Y = ctr("xaobcpw,wdz->xaobcpdz", Y, Rb);
+    Tn bot2 = ctr("xaobcpdz,qz->xaobcpdq", Y, C1);
+    Tn v = ctr("JEkeFufH,JekEfuFH->", up2, bot2);
     ctmk::copy(st, v.p, out, 1);
     ws.release(mk);
 }
@@ -1843,10 +1898,6 @@ ctm_status ctm_magnetization(ctm_ctx* c, double* m)
 ctm_status ctm_bond_correlation(ctm_ctx* c, double* zz)
 {
     if (!c || !zz) return CTM_EINVAL;
-    if (!(c->cfg.flags & CTM_FLAG_REDUCED)) {
-        c->err = "the two-site patch is built for the reduced method (CTM_FLAG_REDUCED) only";
-        return CTM_EINVAL;
-    }
     if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
     double h[2] = {0.0, 0.0};
     ctm_status s = guarded(c, [&] {
