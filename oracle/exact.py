@@ -56,6 +56,16 @@ def product_state_f(beta, sign=+1):
     return -(np.log(h) + onsager_log_kappa(beta)) / beta
 
 
+def product_state_energy(beta, sign=+1):
+    """Internal energy per site U = d(beta f)/d beta of the product state
+    A = |+> (sign=+1) or |-> (sign=-1): beta f = -(ln cosh|sinh + ln kappa_2D),
+    and d ln kappa_2D / d beta is twice Onsager's nearest-neighbour correlation
+    (two links per site of the square lattice).  The first term is the link to
+    the layer whose spin the state leaves free (tanh beta for |+>)."""
+    h = np.tanh(beta) if sign > 0 else 1.0 / np.tanh(beta)
+    return -h - 2.0 * onsager_nn_correlation(beta)
+
+
 def patch_value(a, boundary, Lx, Ly):
     """Contract the Lx x Ly patch of site tensors a[l,u,r,d] whose dangling legs
     all carry the boundary vector.  Row by row, site by site; the state holds the

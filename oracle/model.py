@@ -64,6 +64,34 @@ def pepo_Oz(beta):
     return ein("s,sp,sq,sl,su,sr,sd->pqlurd", sig, s, s, s, s, s, s)
 
 
+def sqrt_W_dbeta(beta):
+    """d sqrt(W) / d beta.  W has the beta-independent eigenvectors (1, 1)/sqrt2
+    and (1, -1)/sqrt2 with eigenvalues 2 cosh(beta) and 2 sinh(beta), so only
+    the square roots of the eigenvalues move: d sqrt(2 cosh b) = sinh b /
+    sqrt(2 cosh b) and d sqrt(2 sinh b) = cosh b / sqrt(2 sinh b)."""
+    if beta <= 0:
+        raise ValueError("W must be positive definite (beta > 0)")
+    Pp = np.array([[0.5, 0.5], [0.5, 0.5]])
+    Pm = np.array([[0.5, -0.5], [-0.5, 0.5]])
+    return (np.sinh(beta) / np.sqrt(2 * np.cosh(beta))) * Pp + (np.cosh(beta) / np.sqrt(2 * np.sinh(beta))) * Pm
+
+
+def pepo_dO(beta):
+    """d O / d beta: the product rule over the six sqrt(W) factors of O.
+
+    Each link's W = sqrt(W) sqrt(W) is split over its two end sites, so the sum
+    over one site's six legs of the single-leg derivatives, in a translation
+    invariant environment, counts every link of the site's three once:
+    -n1(dO) / n1(O) is the internal energy per site (Sec. IV B, U computed with
+    an impurity tensor)."""
+    s, ds = sqrt_W(beta), sqrt_W_dbeta(beta)
+    out = np.zeros((PHYS,) * 6)
+    for k in range(6):
+        mats = [ds if j == k else s for j in range(6)]
+        out += ein("sp,sq,sl,su,sr,sd->pqlurd", *mats)
+    return out
+
+
 def identity_pepo():
     """PEPO of the norm network <psi|psi>: delta_{pq} with in-plane legs of size 1.
 

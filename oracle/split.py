@@ -491,6 +491,19 @@ def magnetization(env, A, beta):
     return float(vals[0] / vals[1])
 
 
+def energy(env, A, beta):
+    """Internal energy per site U = -n1(dO/dbeta) / n1(O) in the converged
+    triple-layer environment env: minus the beta derivative of ln kappa3 at
+    fixed A and environment, which at the optimum of A (f stationary in A) is
+    d(beta f)/d beta (Sec. IV B)."""
+    bot = bottom_row(env)
+    vals = []
+    for O in (model.pepo_dO(beta), model.pepo_O(beta)):
+        _, _, up_bk = upper_sequence(env, A, O)
+        vals.append(ein("wetgz,wgtez->", up_bk, bot))
+    return float(-vals[0] / vals[1])
+
+
 def two_site_value(env, A, O1, O2):
     """The 3 x 4 patch around two horizontally adjacent sites with the PEPOs O1
     (left) and O2 (right): the two-column top row, then the ket, PEPO and bra

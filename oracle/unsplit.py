@@ -146,6 +146,16 @@ def magnetization(C, T, A, beta):
     return float(nz / n1)
 
 
+def energy(C, T, A, beta):
+    """Internal energy per site U = -n1(dO/dbeta) / n1(O): the fused site built
+    with dO/dbeta over the one built with O, in the 3x3 patch of the converged
+    triple-layer environment (C, T)."""
+    env = site_environment(C, T)
+    nd = ein("lurd,lurd->", env, model.fuse_triple(A, model.pepo_dO(beta)))
+    n1 = ein("lurd,lurd->", env, model.fuse_triple(A, model.pepo_O(beta)))
+    return float(-nd / n1)
+
+
 def two_site_value(C, T, a1, a2):
     """The 3 x 4 patch: corners and edges around two horizontally adjacent sites
     a1 (left) and a2 (right), sharing the bond k (a1's right leg, a2's left leg):

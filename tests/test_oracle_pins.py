@@ -123,6 +123,76 @@ def test_product_state_bond_correlation_is_the_2d_one():
     assert abs(unsplit.bond_correlation(C, T, A, beta) - exact.onsager_nn_correlation(beta)) < 1e-11
 
 
+@pytest.mark.parametrize("beta", [0.05, 0.2, 0.7])
+def test_pepo_beta_derivative_is_the_finite_difference(beta):
+    """d sqrt(W)/d beta (closed form in the eigenbasis of W) against central
+    differences of the eigh-based sqrt(W), and dO/d beta (product rule over the
+    six legs) against central differences of O."""
+    h = 1e-6
+    fd = (model.sqrt_W(beta + h) - model.sqrt_W(beta - h)) / (2 * h)
+    assert np.max(np.abs(model.sqrt_W_dbeta(beta) - fd)) < 1e-8
+    fdO = (model.pepo_O(beta + h) - model.pepo_O(beta - h)) / (2 * h)
+    assert np.max(np.abs(model.pepo_dO(beta) - fdO)) < 1e-8 * max(1.0, np.max(np.abs(fdO)))
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+@pytest.mark.parametrize("beta", [0.2, 0.3])
+def test_product_state_energy_is_the_beta_derivative(sign, beta):
+    """The closed-form U of the product states against central differences of
+    beta f(beta), whose 2D part is the quadrature form of ln kappa_2D."""
+    h = 1e-5
+    bf = lambda b: b * exact.product_state_f(b, sign)
+    fd = (bf(beta + h) - bf(beta - h)) / (2 * h)
+    assert abs(exact.product_state_energy(beta, sign) - fd) < 1e-8
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_unsplit_product_state_energy_is_the_closed_form(sign):
+    """For A = (1, +-1)/sqrt(2) the energy impurity gives the 2D Ising energy
+    plus the link to the free neighbouring layer."""
+    beta = 0.2
+    A = model.embed_product_state(2, sign)
+    O = model.pepo_O(beta)
+    C, T, _, _ = unsplit.run(model.fuse_triple(A, O), (2, 2, 2), 24, 400, tol=1e-14)
+    assert abs(unsplit.energy(C, T, A, beta) - exact.product_state_energy(beta, sign)) < 1e-10
+
+
+def test_energy_is_the_beta_derivative_at_fixed_A():
+    """U = -d ln kappa3 / d beta at fixed A: the impurity value in the converged
+    environment against central differences of the re-converged reduced-method
+    ln kappa3 (beta f = -(ln kappa3 - ln kappa2); kappa2 does not depend on
+    beta).  A random D = 2 tensor, chi = 16."""
+    beta, chi, h = 0.2, 16, 1e-5
+    A = model.d4_symmetrize(raw_peps(2, 0))
+    D = A.shape[1]
+
+    def env_and_lk3(b):
+        a3 = model.fuse_triple(A, model.pepo_O(b))
+        C, T, _, _ = unsplit.run(a3, (D, 2, D), chi, 400, tol=1e-13)
+        return C, T, unsplit.log_kappa(C, T, a3)[0]
+
+    C, T, _ = env_and_lk3(beta)
+    U = unsplit.energy(C, T, A, beta)
+    fd = -(env_and_lk3(beta + h)[2] - env_and_lk3(beta - h)[2]) / (2 * h)
+    assert abs(U - fd) < 1e-6 * abs(U), (U, fd)
+
+
+def test_split_energy_is_the_beta_derivative_at_fixed_A():
+    """The same fact for the split environment (D = 2, chi = 16)."""
+    beta, chi, h = 0.2, 16, 1e-5
+    A = model.d4_symmetrize(raw_peps(2, 0))
+
+    def env_and_lk3(b):
+        O = model.pepo_O(b)
+        env, _, _, _ = split.run(A, O, chi, 300, tol=1e-13)
+        return env, split.log_kappa(env, A, O)[0]
+
+    env, _ = env_and_lk3(beta)
+    U = split.energy(env, A, beta)
+    fd = -(env_and_lk3(beta + h)[1] - env_and_lk3(beta - h)[1]) / (2 * h)
+    assert abs(U - fd) < 1e-6 * abs(U), (U, fd)
+
+
 # ------------------------------------------------------ reduced (unsplit) CTM
 
 @pytest.mark.parametrize("n", [1, 2])
@@ -151,6 +221,25 @@ def test_bond_correlation_untruncated_split_equals_unsplit(n):
     env, _, _, _ = split.run(A, O, 10 ** 9, n)
     C, T, _, _ = unsplit.run(model.fuse_triple(A, O), (2, 2, 2), 10 ** 9, n)
     assert abs(split.bond_correlation(env, A, beta) - unsplit.bond_correlation(C, T, A, beta)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_energy_untruncated_split_equals_unsplit(n):
+    """The energy impurity in the split patch and in the fused-site patch:
+    independent codes for the same finite network when nothing is truncated."""
+    beta = 0.2
+    A = model.d4_symmetrize(raw_peps(2, 1))
+    O = model.pepo_O(beta)
+    env, _, _, _ = split.run(A, O, 10 ** 9, n)
+    C, T, _, _ = unsplit.run(model.fuse_triple(A, O), (2, 2, 2), 10 ** 9, n)
+    assert abs(split.energy(env, A, beta) - unsplit.energy(C, T, A, beta)) < 1e-12
+
+
+def test_split_product_state_energy_is_the_closed_form():
+    beta = 0.2
+    P = model.embed_product_state(2, +1)
+    env, _, _, _ = split.run(P, model.pepo_O(beta), 16, 300, tol=1e-13)
+    assert abs(split.energy(env, P, beta) - exact.product_state_energy(beta, +1)) < 1e-10
 
 
 def test_split_product_state_bond_correlation_is_onsagers():
