@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CTM_ABI_VERSION 4
+#define CTM_ABI_VERSION 5
 
 typedef struct ctm_ctx ctm_ctx;
 
@@ -186,6 +186,17 @@ ctm_status ctm_magnetization(ctm_ctx* c, double* m);
  * before any iteration, CTM_ENUMERIC when the patch value is zero or
  * non-finite. */
 ctm_status ctm_bond_correlation(ctm_ctx* c, double* zz);
+
+/* Internal energy per site U (Sec. IV B: U from an impurity tensor in the
+ * converged environment; J = 1, three links per site):
+ * U = -n1(dO/dbeta) / n1(O), the 3x3 patch of the triple-layer network with
+ * the centre PEPO replaced by its beta derivative (product rule over the six
+ * sqrt(W) legs), divided by the same patch with O.  This is -d ln kappa3 /
+ * d beta at fixed A, i.e. d(beta f)/d beta wherever f is stationary in A (at
+ * the variational optimum).  Both methods.  *u receives the host double.
+ * CTM_ESTATE before any iteration, CTM_ENUMERIC when the patch value is zero
+ * or non-finite. */
+ctm_status ctm_energy(ctm_ctx* c, double* u);
 
 /* Launch statistics of a context built with CTM_FLAG_PROFILE: which = 0 the
  * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernels, 2 the Cholesky QR kernels,

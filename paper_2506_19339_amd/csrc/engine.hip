@@ -1881,7 +1881,7 @@ ctm_status ctm_magnetization(ctm_ctx* c, double* m)
         const Arena::Mark mk = W.ws.mark();
         double* Oz = W.ws.alloc(64);
         double* val = W.ws.alloc(2);
-        ctmk::ising_pepo(W.st, Oz, c->beta, true);
+        ctmk::ising_pepo(W.st, Oz, c->beta, ctmk::PEPO_SPIN);
         W.centre_value(c->net[0], Oz, val + 0);
         W.centre_value(c->net[0], c->net[0].O, val + 1);
         HIPCHK(hipMemcpyAsync(h, val, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
@@ -1892,6 +1892,31 @@ ctm_status ctm_magnetization(ctm_ctx* c, double* m)
             throw CtmError(CTM_ENUMERIC, "zero or non-finite network value");
     });
     if (s == CTM_OK) *m = h[0] / h[1];
+    return s;
+}
+
+ctm_status ctm_energy(ctm_ctx* c, double* u)
+{
+    if (!c || !u) return CTM_EINVAL;
+    if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
+    double h[2] = {0.0, 0.0};
+    ctm_status s = guarded(c, [&] {
+        c->fork();
+        Worker& W = c->w[0];
+        const Arena::Mark mk = W.ws.mark();
+        double* dO = W.ws.alloc(64);
+        double* val = W.ws.alloc(2);
+        ctmk::ising_pepo(W.st, dO, c->beta, ctmk::PEPO_DBETA);
+        W.centre_value(c->net[0], dO, val + 0);
+        W.centre_value(c->net[0], c->net[0].O, val + 1);
+        HIPCHK(hipMemcpyAsync(h, val, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
+        HIPCHK(hipStreamSynchronize(W.st));
+        W.ws.release(mk);
+        c->join();
+        if (!(h[1] != 0.0) || !std::isfinite(h[0] / h[1]))
+            throw CtmError(CTM_ENUMERIC, "zero or non-finite network value");
+    });
+    if (s == CTM_OK) *u = -h[0] / h[1];
     return s;
 }
 
@@ -1906,7 +1931,7 @@ ctm_status ctm_bond_correlation(ctm_ctx* c, double* zz)
         const Arena::Mark mk = W.ws.mark();
         double* Oz = W.ws.alloc(64);
         double* val = W.ws.alloc(2);
-        ctmk::ising_pepo(W.st, Oz, c->beta, true);
+        ctmk::ising_pepo(W.st, Oz, c->beta, ctmk::PEPO_SPIN);
         W.pair_value(c->net[0], Oz, val + 0);
         W.pair_value(c->net[0], c->net[0].O, val + 1);
         HIPCHK(hipMemcpyAsync(h, val, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));

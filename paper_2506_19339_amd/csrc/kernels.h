@@ -81,7 +81,8 @@ void diag_inv_sqrt(hipStream_t s, const double* G, int n, double* d);
 void count_above(hipStream_t s, const double* S, int n, double cutoff, int* out);
 void randn(hipStream_t s, double* x, int64_t n, uint64_t seed);
 void d4_project(hipStream_t s, const double* A, double* out, int D);
-void ising_pepo(hipStream_t s, double* O, double beta, bool impurity = false);
+enum { PEPO_PLAIN = 0, PEPO_SPIN = 1, PEPO_DBETA = 2 };
+void ising_pepo(hipStream_t s, double* O, double beta, int kind = PEPO_PLAIN);
 void identity_pepo(hipStream_t s, double* O);
 // reduced method: fused site tensor (Df = D dd D per leg), bra environment
 // from the fused-site environment, chi-leg symmetrisation of an edge tensor

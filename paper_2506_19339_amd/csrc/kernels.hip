@@ -980,29 +980,42 @@ void d4_project(hipStream_t s, const double* A, double* out, int D)
 // O[p,q,l,u,r,d] = sum_s w[s,p] w[s,q] w[s,l] w[s,u] w[s,r] w[s,d], w = sqrt(W),
 // W = [[e^b, e^-b], [e^-b, e^b]]: eigenvalues 2cosh b (vector (1,1)/sqrt2) and
 // 2sinh b (vector (1,-1)/sqrt2), so w = (sqrt(2cosh b) P+ + sqrt(2sinh b) P-).
-// impurity = 1: the spin's value sigma(s) = +1 (s = 0), -1 (s = 1) under the
-// sum (impurity tensor of the local magnetisation)
-__global__ void ising_pepo_kernel(double* O, double beta, int impurity)
+// kind PEPO_SPIN: the spin's value sigma(s) = +1 (s = 0), -1 (s = 1) under the
+// sum (impurity tensor of the local magnetisation).  kind PEPO_DBETA: dO/dbeta,
+// the product rule over the six legs with dw = (sinh b / sqrt(2cosh b)) P+ +
+// (cosh b / sqrt(2sinh b)) P- (impurity tensor of the internal energy).
+__global__ void ising_pepo_kernel(double* O, double beta, int kind)
 {
     const int i = threadIdx.x;
     if (i >= 64) return;
     const double a = sqrt(2.0 * cosh(beta)), b = sqrt(2.0 * sinh(beta));
     const double w[2][2] = {{0.5 * (a + b), 0.5 * (a - b)}, {0.5 * (a - b), 0.5 * (a + b)}};
+    const double da = sinh(beta) / a, db = cosh(beta) / b;
+    const double dw[2][2] = {{0.5 * (da + db), 0.5 * (da - db)}, {0.5 * (da - db), 0.5 * (da + db)}};
     int idx[6];
     int rem = i;
     for (int k = 5; k >= 0; --k) { idx[k] = rem & 1; rem >>= 1; }
     double acc = 0.0;
     for (int s = 0; s < 2; ++s) {
-        double t = (impurity && s == 1) ? -1.0 : 1.0;
-        for (int k = 0; k < 6; ++k) t *= w[s][idx[k]];
-        acc += t;
+        if (kind == PEPO_DBETA) {
+            for (int k = 0; k < 6; ++k) {
+                double t = dw[s][idx[k]];
+                for (int j = 0; j < 6; ++j)
+                    if (j != k) t *= w[s][idx[j]];
+                acc += t;
+            }
+        } else {
+            double t = (kind == PEPO_SPIN && s == 1) ? -1.0 : 1.0;
+            for (int k = 0; k < 6; ++k) t *= w[s][idx[k]];
+            acc += t;
+        }
     }
     O[i] = acc;
 }
 
-void ising_pepo(hipStream_t s, double* O, double beta, bool impurity)
+void ising_pepo(hipStream_t s, double* O, double beta, int kind)
 {
-    hipLaunchKernelGGL(ising_pepo_kernel, dim3(1), dim3(64), 0, s, O, beta, impurity ? 1 : 0);
+    hipLaunchKernelGGL(ising_pepo_kernel, dim3(1), dim3(64), 0, s, O, beta, kind);
 }
 
 __global__ void identity_pepo_kernel(double* O)

@@ -71,6 +71,7 @@ def load_library(path=None):
     lib.ctm_grad.argtypes = [vp, vp]
     lib.ctm_magnetization.argtypes = [vp, dp]
     lib.ctm_bond_correlation.argtypes = [vp, dp]
+    lib.ctm_energy.argtypes = [vp, dp]
     lib.ctm_corner_spectrum.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.ctm_reset_tensor.argtypes = [vp, ctypes.c_double, vp]
     lib.ctm_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong)]
@@ -180,10 +181,16 @@ class SplitCTM:
         return m.value
 
     def bond_correlation(self):
-        """In-plane nearest-neighbour <sigma sigma'> (reduced-method contexts)."""
+        """In-plane nearest-neighbour <sigma sigma'> of two PEPO-layer spins."""
         zz = ctypes.c_double()
         self._check(self._lib.ctm_bond_correlation(self._ctx, ctypes.byref(zz)))
         return zz.value
+
+    def energy(self):
+        """Internal energy per site U = -d ln kappa3 / d beta at fixed A."""
+        u = ctypes.c_double()
+        self._check(self._lib.ctm_energy(self._ctx, ctypes.byref(u)))
+        return u.value
 
     def spectrum(self, which=3):
         cap = 4096

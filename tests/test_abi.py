@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_only_calls():
     from paper_2506_19339_amd import ctm
     lib = ctm.load_library()
-    assert lib.ctm_abi_version() == 4
+    assert lib.ctm_abi_version() == 5
     assert lib.ctm_status_string(0) == b"ok"
     assert lib.ctm_status_string(4) == b"not converged"
     lib.ctm_destroy(None)                          # NULL-safe

@@ -1,8 +1,10 @@
 """Impurity observables in the converged triple-layer environment: the site
-magnetisation (ctm_magnetization, split and reduced method) and the in-plane
-nearest-neighbour correlation (ctm_bond_correlation, both methods), against
-the oracle on the same inputs, the spin-flip symmetry and, for the symmetric
-product state, Onsager's nearest-neighbour correlation."""
+magnetisation (ctm_magnetization), the in-plane nearest-neighbour correlation
+(ctm_bond_correlation) and the internal energy per site (ctm_energy), each for
+the split and the reduced method, against the oracle on the same inputs, the
+spin-flip symmetry, the product states' closed forms (Onsager's
+nearest-neighbour correlation, the product-state energy) and, for the energy,
+central differences of the GPU's own ln kappa3 in beta."""
 import numpy as np
 import pytest
 
@@ -99,4 +101,65 @@ def test_bond_correlation_before_iterating_is_a_state_error():
     with ctm.SplitCTM(0.2, raw_peps(2, 0), 8) as c:
         with pytest.raises(ctm.CtmError) as e:
             c.bond_correlation()
+        assert e.value.status == ctm.CTM_ESTATE
+
+
+@pytest.mark.parametrize("method", ["split", "reduced"])
+@pytest.mark.parametrize("beta,D,chi,n,seed", [(0.2, 2, 12, 20, 1), (0.22, 3, 20, 15, 2)])
+def test_energy_vs_oracle(method, beta, D, chi, n, seed):
+    A = raw_peps(D, seed)
+    with ctm.SplitCTM(beta, A, chi, svd_cutoff=CUT, method=method) as c:
+        assert c.iterate(n)[0] == n
+        u = c.energy()
+    As = model.d4_symmetrize(A)
+    O = model.pepo_O(beta)
+    if method == "split":
+        env, _, _, _ = split.run(As, O, chi, n, cutoff=CUT)
+        uo = split.energy(env, As, beta)
+    else:
+        C, T, _, _ = unsplit.run(model.fuse_triple(As, O), (D, 2, D), chi, n)
+        uo = unsplit.energy(C, T, As, beta)
+    assert abs(u - uo) <= 1e-10 * abs(uo), (u, uo)
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+@pytest.mark.parametrize("method,chi,tol", [("split", 16, 1e-9), ("reduced", 24, 1e-10)])
+def test_energy_of_the_product_states_is_the_closed_form(method, chi, tol, sign):
+    """A = (1, +-1)/sqrt(2): 2D Ising energy per site plus the link to the layer
+    the state leaves free (tanh beta, resp. coth beta)."""
+    beta = 0.2
+    with ctm.SplitCTM(beta, model.embed_product_state(2, sign), chi, max_iter=400, tol=1e-13, svd_cutoff=CUT,
+                      method=method) as c:
+        assert c.iterate(0)[2]
+        u = c.energy()
+    assert abs(u - exact.product_state_energy(beta, sign)) <= tol, (u, exact.product_state_energy(beta, sign))
+
+
+@pytest.mark.parametrize("method,rtol", [("split", 5e-5), ("reduced", 1e-6)])
+def test_energy_is_the_beta_derivative_of_ln_kappa3(method, rtol):
+    """U = -d ln kappa3 / d beta at fixed A: the impurity value against central
+    differences of the library's own converged ln kappa3 at beta +- h (warm
+    restarts with ctm_reset_tensor), D = 3, chi = 30: several tiles and ragged
+    tails in every product.  The impurity value differentiates the 3x3 patch
+    only, which is exact for a stationary infinite environment; at finite chi
+    the two differ by the environment's truncation gap, as for the gradient:
+    6.8e-6 relative for the split environment here, hence its bar."""
+    beta, chi, h = 0.21, 30, 1e-5
+    A = model.d4_symmetrize(raw_peps(3, 4))
+    with ctm.SplitCTM(beta, A, chi, max_iter=400, tol=1e-12, svd_cutoff=CUT, method=method) as c:
+        assert c.iterate(0)[2]
+        u = c.energy()
+        lk = []
+        for b in (beta + h, beta - h):
+            c.reset_tensor(b, A)
+            assert c.iterate(0)[2]
+            lk.append(c.free_energy()[1])
+    fd = -(lk[0] - lk[1]) / (2 * h)
+    assert abs(u - fd) <= rtol * abs(u), (u, fd)
+
+
+def test_energy_before_iterating_is_a_state_error():
+    with ctm.SplitCTM(0.2, raw_peps(2, 0), 8) as c:
+        with pytest.raises(ctm.CtmError) as e:
+            c.energy()
         assert e.value.status == ctm.CTM_ESTATE
