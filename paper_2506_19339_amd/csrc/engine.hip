@@ -509,8 +509,11 @@ struct Worker {
             pd.is[k] = istride[pos];
         }
         Tn out = tmp_dims(od, A.r);
-        if (trace_perm && out.n() >= trace_perm)
-            std::fprintf(stderr, "permute %s->%s %lld\n", li.c_str(), lo.c_str(), (long long)out.n());
+        if (trace_perm && out.n() >= trace_perm) {
+            std::fprintf(stderr, "permute %s->%s %lld [", li.c_str(), lo.c_str(), (long long)out.n());
+            for (int k = 0; k < A.r; ++k) std::fprintf(stderr, k ? " %lld" : "%lld", (long long)A.d[k]);
+            std::fprintf(stderr, "]\n");
+        }
         ctmk::permute(st, A.p, out.p, pd, out.n());
         return out;
     }
