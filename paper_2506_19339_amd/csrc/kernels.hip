@@ -14,9 +14,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.h"
+#include "perm_plan.h"
 
 namespace ctmk {
 
@@ -547,6 +549,110 @@ __global__ void permute32_kernel(const double* __restrict__ in, double* __restri
     }
 }
 
+// testing aid: CTM_NO_TILED_PERMUTE=1 keeps every permute element-wise
+static bool no_tiled_permute()
+{
+    static const bool off = std::getenv("CTM_NO_TILED_PERMUTE") != nullptr;
+    return off;
+}
+
+// LDS-tiled form (plan in perm_plan.h): one tile per iteration of a
+// grid-stride loop.  Per tile the 32-bit offsets of the out-block chunk in the
+// input (itab) and of the in-block chunk in the output (otab) are decoded once.
+// Load: one wave per LDS row (one out-block element), lanes along the in-block
+// chunk x unit, contiguous in the input; store: one wave per in-block element,
+// lanes along the out-block chunk x unit, contiguous in the output.  The LDS
+// rows have an odd pitch.  Divisions by runtime values use multiply-shift.
+__device__ inline uint32_t fdiv(uint32_t x, const FastDiv& f)
+{
+    return (__umulhi(x, f.mul) + x) >> f.shr;
+}
+
+constexpr int kPermPerThread = kPermTileElems / 256;
+
+__global__ __launch_bounds__(256) void permute_tile_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                           PermTile t)
+{
+    __shared__ double buf[kPermTileElems + kPermTileSide + 1];
+    __shared__ uint32_t itab[kPermTileSide], otab[kPermTileSide];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+    const int U = t.U, P = (t.TI * t.U) | 1;
+    for (uint32_t tile = blockIdx.x; tile < (uint32_t)t.tiles; tile += gridDim.x) {
+        uint32_t r = fdiv(tile, t.fco);
+        const int co = (int)(tile - r * t.fco.d);
+        uint32_t r2 = fdiv(r, t.fci);
+        const int ci = (int)(r - r2 * t.fci.d);
+        r = r2;
+        uint32_t ib = 0, ob = 0;
+        for (int k = 0; k < t.nrest; ++k) {
+            const uint32_t q = fdiv(r, t.rest_d[k]);
+            const uint32_t c = r - q * t.rest_d[k].d;
+            r = q;
+            ib += c * (uint32_t)t.rest_is[k];
+            ob += c * (uint32_t)t.rest_os[k];
+        }
+        const int i0 = ci * t.TI, o0 = co * t.TO;
+        const int ti = min(t.TI, t.Lin - i0), to = min(t.TO, t.Lout - o0);
+        for (int o = tid; o < to; o += blockDim.x) {
+            uint32_t x = (uint32_t)(o0 + o), off = 0;
+            for (int k = 0; k < t.nout; ++k) {
+                const uint32_t q = x / (uint32_t)t.out_d[k];
+                off += (x - q * (uint32_t)t.out_d[k]) * (uint32_t)t.out_is[k];
+                x = q;
+            }
+            itab[o] = off;
+        }
+        for (int i = tid; i < ti; i += blockDim.x) {
+            uint32_t x = (uint32_t)(i0 + i), off = 0;
+            for (int k = 0; k < t.nin; ++k) {
+                const uint32_t q = x / (uint32_t)t.in_d[k];
+                off += (x - q * (uint32_t)t.in_d[k]) * (uint32_t)t.in_os[k];
+                x = q;
+            }
+            otab[i] = off;
+        }
+        __syncthreads();
+        // load: every thread issues its (up to kPermPerThread) reads before
+        // writing any of them to LDS, so that they are in flight together
+        const FastDiv& fr = t.frun[ci == t.nci - 1 ? 1 : 0];
+        const int run = (int)fr.d, tot = to * run;
+        const uint32_t ibase = ib + (uint32_t)i0 * (uint32_t)U;
+        double v[kPermPerThread];
+#pragma unroll
+        for (int k = 0; k < kPermPerThread; ++k) {
+            const int e = tid + k * 256;
+            if (e < tot) {
+                const int o = (int)fdiv((uint32_t)e, fr);
+                v[k] = in[ibase + itab[o] + (uint32_t)(e - o * run)];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPermPerThread; ++k) {
+            const int e = tid + k * 256;
+            if (e < tot) {
+                const int o = (int)fdiv((uint32_t)e, fr);
+                buf[o * P + (e - o * run)] = v[k];
+            }
+        }
+        __syncthreads();
+        // store: row i of the output tile (one in-block element) is contiguous
+        const FastDiv& fo = t.fruno[co == t.nco - 1 ? 1 : 0];
+        const int runo = (int)fo.d, toto = ti * runo;
+        const uint32_t obase = ob + (uint32_t)o0 * (uint32_t)U;
+#pragma unroll
+        for (int k = 0; k < kPermPerThread; ++k) {
+            const int e = tid + k * 256;
+            if (e < toto) {
+                const int i = (int)fdiv((uint32_t)e, fo);
+                const int w = e - i * runo;
+                const int o = (int)fdiv((uint32_t)w, t.fU);
+                out[obase + otab[i] + (uint32_t)w] = buf[o * P + i * U + (w - o * U)];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 static int grid_for(int64_t n, int block = 256, int cap = 8192)
 {
     int64_t g = (n + block - 1) / block;
@@ -563,7 +669,11 @@ void permute(hipStream_t s, const double* in, double* out, const PermDesc& pd, i
     int64_t span = 1;   // largest input offset + 1
     for (int k = 0; k < pd.rank; ++k) span += (pd.od[k] - 1) * pd.is[k];
     small = small && span < lim;
-    if (small) {
+    PermTile pt{};
+    if (small && !no_tiled_permute() && plan_perm_tile(pd.rank, pd.od, pd.is, pt)) {
+        const int g = (int)std::min<int64_t>(pt.tiles, 4096);
+        hipLaunchKernelGGL(permute_tile_kernel, dim3(g), dim3(256), 0, s, in, out, pt);
+    } else if (small) {
         PermDesc32 p32{};
         p32.rank = pd.rank;
         for (int k = 0; k < pd.rank; ++k) {

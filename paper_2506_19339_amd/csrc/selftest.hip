@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "perm_plan.h"
 
 namespace {
 template <class T>
@@ -104,6 +105,23 @@ int ctm_selftest_gemm_lp(int prec, int ta, int tb, int M, int N, int K, int batc
     (void)hipFree(dC);
     if (dW) (void)hipFree(dW);
     return rc;
+}
+
+// 1 when ctmk::permute takes the LDS-tiled form for transpose(dims, axes)
+// (same arguments as ctm_selftest_permute), 0 otherwise
+int ctm_selftest_permute_tiled(int rank, const long long* dims, const int* axes)
+{
+    int64_t n = 1, stride[12], od[12], is[12];
+    for (int k = rank - 1; k >= 0; --k) {
+        stride[k] = n;
+        n *= dims[k];
+    }
+    for (int k = 0; k < rank; ++k) {
+        od[k] = dims[axes[k]];
+        is[k] = stride[axes[k]];
+    }
+    ctmk::PermTile t{};
+    return ctmk::plan_perm_tile(rank, od, is, t) ? 1 : 0;
 }
 
 // out = transpose(in, axes): in has dims[0..rank-1] (row-major), out axis k is

@@ -23,6 +23,8 @@ def lib():
     L.ctm_selftest_gemm_lp.argtypes = [ctypes.c_int] * 7 + [dp, dp, dp, ctypes.c_longlong]
     L.ctm_selftest_permute.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
                                        ctypes.POINTER(ctypes.c_int), dp, dp]
+    L.ctm_selftest_permute_tiled.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                             ctypes.POINTER(ctypes.c_int)]
     L.ctm_selftest_gemm_splits.argtypes = [ctypes.c_int] * 4 + [ctypes.c_longlong]
     L.ctm_selftest_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
     L.ctm_selftest_cholqr.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
@@ -108,6 +110,59 @@ def test_permute_matches_numpy(lib, dims, axes):
     a = (ctypes.c_int * len(axes))(*axes)
     assert lib.ctm_selftest_permute(len(dims), d, a, _p(np.ascontiguousarray(x)), _p(out)) == 0
     assert np.array_equal(out.reshape([dims[k] for k in axes]), np.transpose(x, axes))
+
+
+# permutes of the split-CTMRG move (labels of the contraction code, D = 5,
+# d = 2; chi = 100, or 60 for the two largest), and random ones
+TRACED_PERMUTES = [
+    ("vqurkzsbe", "urkzsevqb", (5, 2, 2, 2, 60, 5, 5, 5, 60), 1),
+    ("rnqstbfwv", "rnstfvqwb", (5, 5, 2, 2, 2, 5, 60, 5, 60), 1),
+    ("rnstfvhe", "rnstfhve", (5, 5, 2, 2, 100, 100, 5, 5), 1),
+    ("vadpqurkl", "vdqurkapl", (5, 5, 100, 2, 2, 1, 1, 100, 5), 1),
+    ("vdqurkzs", "vqurkzsd", (5, 100, 2, 2, 2, 100, 5, 5), 1),
+    ("ibfprnmj", "bfrnjipm", (2, 5, 100, 2, 5, 5, 2, 100), 1),
+    ("fblnhqmt", "fblqmhtn", (100, 5, 5, 5, 100, 2, 2, 2), 0),   # output runs of 5: element-wise
+    ("sonbpmd", "nmdpbos", (5, 2, 100, 100, 2, 5, 5), 1),
+]
+
+
+def _permute_case(lib, dims, axes, seed):
+    x = np.random.default_rng(seed).standard_normal(dims)
+    out = np.zeros(int(np.prod(dims)))
+    d = (ctypes.c_longlong * len(dims))(*dims)
+    a = (ctypes.c_int * len(axes))(*axes)
+    assert lib.ctm_selftest_permute(len(dims), d, a, _p(np.ascontiguousarray(x)), _p(out)) == 0
+    assert np.array_equal(out.reshape([dims[k] for k in axes]), np.transpose(x, axes)), (dims, axes)
+    return lib.ctm_selftest_permute_tiled(len(dims), d, a)
+
+
+@pytest.mark.parametrize("li,lo,dims,tiled", TRACED_PERMUTES)
+def test_tiled_permute_of_the_move(lib, li, lo, dims, tiled):
+    """The permutes of the contraction code: bit-exact against numpy, in the
+    form (LDS-tiled or element-wise) the plan gives them."""
+    axes = tuple(li.index(c) for c in lo)
+    assert _permute_case(lib, dims, axes, 3) == tiled
+
+
+def test_random_permutes_tiled_and_elementwise(lib):
+    """120 random permutations (rank 1-9, dims from a pool with ragged sizes,
+    up to 1.5e6 elements): bit-exact against numpy in both forms; at least a
+    quarter of them take the tiled form."""
+    rng = np.random.default_rng(17)
+    pool = [1, 2, 2, 3, 5, 5, 7, 16, 33, 100, 144]
+    tiled = 0
+    for case in range(120):
+        rank = int(rng.integers(1, 10))
+        dims, n = [], 1
+        for _ in range(rank):
+            v = int(rng.choice(pool))
+            if n * v > 1_500_000:
+                v = int(rng.integers(1, 4))
+            dims.append(v)
+            n *= v
+        axes = tuple(int(a) for a in rng.permutation(rank))
+        tiled += _permute_case(lib, tuple(dims), axes, case)
+    assert tiled >= 30, tiled
 
 
 def _round_bf16(x):

@@ -1,0 +1,40 @@
+"""Host-side plan of the LDS-tiled permute (no device work): which permutes take
+the tiled form, through the self-test library's planner hook."""
+import ctypes
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SELFTEST = os.path.join(ROOT, "paper_2506_19339_amd", "libctm_selftest.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(SELFTEST):
+        pytest.skip("libctm_selftest.so not built")
+    L = ctypes.CDLL(SELFTEST)
+    L.ctm_selftest_permute_tiled.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                             ctypes.POINTER(ctypes.c_int)]
+    return L
+
+
+def tiled(lib, dims, axes):
+    d = (ctypes.c_longlong * len(dims))(*dims)
+    a = (ctypes.c_int * len(axes))(*axes)
+    return lib.ctm_selftest_permute_tiled(len(dims), d, a)
+
+
+@pytest.mark.parametrize("dims,axes,want", [
+    ((100, 64), (1, 0), 1),                          # plain transpose
+    ((20000, 100), (1, 0), 1),
+    ((5, 5, 100, 100, 5, 5), (0, 1, 4, 3, 2, 5), 1),  # shared unit of 5 (the last axis stays last)
+    ((100, 100), (0, 1), 0),                         # identity
+    ((3, 1000), (0, 1), 0),
+    ((8, 64, 64), (1, 0, 2), 0),                     # unit of 64 contiguous in both: element-wise
+    ((2, 3), (1, 0), 0),                             # too short for a tile
+    ((100, 5, 5, 5, 100, 2, 2, 2), (0, 1, 2, 5, 6, 4, 7, 3), 0),   # output runs of 5
+    ((7,), (0,), 0),
+])
+def test_plan_choice(lib, dims, axes, want):
+    assert tiled(lib, dims, axes) == want
