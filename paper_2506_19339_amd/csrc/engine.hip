@@ -807,23 +807,26 @@ struct Worker {
         // better start than random normals (fewer power steps).
         const size_t nr = rnd.size();
         std::vector<Tn> Pt(nr), Qt(nr);
-        bool all_warm = true;
+        bool all_warm = true, all_full = true;
         for (size_t j = 0; j < nr; ++j) {
             const SvdReq& r = rq[rnd[j]];
             const int64_t m = r.M.d[0], n = r.M.d[1], mn = std::min(m, n);
             const int64_t k = std::min<int64_t>(
                 std::max<int64_t>(std::min<int64_t>(2 * r.kk, kCoreMax), r.kk + kOversample), mn);
             Pt[j] = tmp({k, n});
-            ctmk::randn(st, Pt[j].p, k * n, 0x5eedull + 7919ull * (++svd_calls));
+            ++svd_calls;
             // a slot starts from its last basis once the network's spectrum
             // moves by less than kWarmGate per move; earlier, while the
             // environment still changes a lot, it starts from fresh normals
             const bool use = warm_starts && r.slot >= 0 && last_delta < kWarmGate;
             const Warm* w = use ? &warm[r.slot] : nullptr;
-            if (w && w->valid && w->n == n && w->kk <= k)
+            const bool warm_ok = w && w->valid && w->n == n && w->kk <= k;
+            const bool full = warm_ok && w->kk == k;
+            if (!full) ctmk::randn(st, Pt[j].p, k * n, 0x5eedull + 7919ull * svd_calls);
+            if (warm_ok)
                 ctmk::copy(st, w->V, Pt[j].p, w->kk * n);   // last move's Ritz vectors first
-            else
-                all_warm = false;
+            all_warm = all_warm && warm_ok;
+            all_full = all_full && full;
         }
         // inside the power steps one Cholesky-QR pass keeps the basis well
         // conditioned; the bases that enter the Rayleigh-Ritz core (last P, Q)
@@ -831,7 +834,8 @@ struct Worker {
         const int q = cfg.power_iters > 0 ? cfg.power_iters : (all_warm ? kWarmPowerIters : 10);
         std::vector<Tn> Ms(nr);
         for (size_t j = 0; j < nr; ++j) Ms[j] = rq[rnd[j]].M;
-        cholqr_pass(Pt);
+        // a whole last-move Ritz basis has orthonormal rows already
+        if (!all_full) cholqr_pass(Pt);
         for (int it = 0; it < q; ++it) {
             Qt = mm_group(Pt, false, Ms, true);    // (M P)^T
             cholqr_pass(Qt);
