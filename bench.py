@@ -151,7 +151,7 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
+        print("bench.py runs on one GPU: the library has no multi-GPU path "
               "(independent evaluations would shard one per GPU)", file=sys.stderr)
         sys.exit(2)
 
