@@ -163,3 +163,33 @@ def test_energy_before_iterating_is_a_state_error():
         with pytest.raises(ctm.CtmError) as e:
             c.energy()
         assert e.value.status == ctm.CTM_ESTATE
+
+
+def test_observables_at_the_d5_chi100_workload():
+    """The evaluation workload (beta = 0.22, D = 5, chi = 100), split method,
+    converged to tol 1e-9, checked through properties that hold at any size
+    (no oracle run at this size): flipping the physical index of A flips the
+    sign of the magnetisation and leaves the bond correlation and the energy
+    unchanged; U matches central differences of the library's own ln kappa3
+    in beta (h = 1e-4, warm restarts) within the finite-chi gap measured for
+    the gradient at this size (1e-4 .. 5e-4), bar 1e-3."""
+    from synth_inputs import WORKLOADS, workload_peps
+    w = WORKLOADS["d5_chi100"]
+    beta, chi, h = w["beta"], w["chi"], 1e-4
+    A = model.d4_symmetrize(workload_peps("d5_chi100"))
+    vals = []
+    for T in (A, A[::-1].copy()):
+        with ctm.SplitCTM(beta, T, chi, max_iter=w["max_iter"], tol=w["tol"], svd_cutoff=CUT) as c:
+            assert c.iterate(0)[2]
+            vals.append((c.magnetization(), c.bond_correlation(), c.energy()))
+            if len(vals) == 1:
+                lk = []
+                for b in (beta + h, beta - h):
+                    c.reset_tensor(b, T)
+                    assert c.iterate(0)[2]
+                    lk.append(c.free_energy()[1])
+    (m, zz, u), (mf, zzf, uf) = vals
+    assert abs(m + mf) <= 1e-8 and abs(zz - zzf) <= 1e-8 and abs(u - uf) <= 1e-8 * abs(u), vals
+    assert abs(zz) <= 1.0 and abs(m) <= 1.0
+    fd = -(lk[0] - lk[1]) / (2 * h)
+    assert abs(u - fd) <= 1e-3 * abs(u), (u, fd)
