@@ -126,6 +126,17 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int kbeg, int kend, doub
             }
 }
 
+// Workgroups go to the 8 XCDs round-robin (linear id mod 8), and each XCD
+// has its own L2.  xcd_remap(b, n) gives XCD k the contiguous range of tile
+// ids [k q + min(k, r), (k + 1) q + min(k + 1, r)) in order (q = n / 8,
+// r = n % 8): neighbouring tiles, which share an operand panel, run on one
+// XCD and read it from that XCD's L2.  It is a bijection of [0, n).
+__device__ inline int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, k = b & 7, j = b >> 3;
+    return k * q + min(k, r) + j;
+}
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256, 4) void gemm_f64_kernel(
     int M, int N, int K, double alpha,
@@ -136,7 +147,9 @@ __global__ __launch_bounds__(256, 4) void gemm_f64_kernel(
 {
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
-    const int z = blockIdx.z;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int tx = t % gx, ty = (t / gx) % gy, z = t / (gx * gy);
     const int bz = z / ksplit, sp = z % ksplit;
     const int kbeg = sp * kchunk;
     const int kend = min(K, kbeg + kchunk);
@@ -145,7 +158,7 @@ __global__ __launch_bounds__(256, 4) void gemm_f64_kernel(
     if (ksplit > 1) { out = P + (int64_t)z * M * N; ldo = N; }
     else { out = C + bz * sC; ldo = ldc; }
     gemm_tile<TA, TB>(M, N, kbeg, kend, alpha, A + bz * sA, lda, B + bz * sB, ldb, beta,
-                      !(beta == 0.0 || ksplit > 1), out, ldo, blockIdx.y * GT, blockIdx.x * GT, As, Bs);
+                      !(beta == 0.0 || ksplit > 1), out, ldo, ty * GT, tx * GT, As, Bs);
 }
 
 // Grouped form: problem i owns the blocks [start[i], start[i + 1]) of a 1-D
@@ -166,7 +179,7 @@ __global__ __launch_bounds__(256, 4) void gemm_f64_group_kernel(GemmGroupDev g, 
 {
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
-    const int b = blockIdx.x;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     int i = 0;
     while (i + 1 < g.n && b >= g.start[i + 1]) ++i;
     const GemmProb q = g.p[i];
@@ -370,13 +383,15 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(
     constexpr int PAD = (P == 1) ? 1 : 8;        // keeps 16-byte alignment of bf16 k-runs
     __shared__ __attribute__((aligned(16))) elem As[GT][LK + PAD];
     __shared__ __attribute__((aligned(16))) elem Bs[GT][LK + PAD];
-    const int z = blockIdx.z;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int z = t / (gx * gy);
     const int bz = z / ksplit, sp = z % ksplit;
     A += bz * sA;
     B += bz * sB;
     const int kbeg = sp * kchunk;
     const int kend = min(K, kbeg + kchunk);
-    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int m0 = ((t / gx) % gy) * GT, n0 = (t % gx) * GT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     flt4 acc[2][2];
