@@ -17,8 +17,8 @@
 
 namespace ctmk {
 
-constexpr int kPermTileElems = 4096;   // doubles per tile (32 KiB of LDS)
-constexpr int kPermTileSide = 512;     // largest chunk of either block
+constexpr int kPermTileElems = 2048;   // doubles per tile (16 KiB of LDS)
+constexpr int kPermTileSide = 256;     // largest chunk of either block
 constexpr int kPermBlockDims = 4;
 constexpr int kPermRestDims = 12;
 
