@@ -1673,6 +1673,10 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
     const double tol = 2.0 * sqrt((double)m) * 2.220446049250313e-16;
     const double tol2 = tol * tol;
 
+    // largest (gamma^2 / alpha beta) and whether any rotation happened, of
+    // this thread's pairs in the current sweep (published once per sweep)
+    float my_max = 0.0f;
+    bool my_rot = false;
     // rotation of the pair held in (L, R), then swap of their positions:
     // L <- s L + c R, R <- c L - s R; lid / rid follow the columns
     auto rotate = [&](double (&Lx)[RL], double (&Rx)[RL], double (&Lv)[RL], double (&Rv)[RL], int& lid, int& rid,
@@ -1694,10 +1698,8 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             c = 1.0 / sqrt(1.0 + t * t);
             sn = c * t;
-            if (l16 == 0) {
-                rotated = 1;
-                atomicMax(&maxr, __float_as_uint((float)(ga * ga / (al * be))));
-            }
+            my_rot = true;
+            my_max = fmaxf(my_max, (float)(ga * ga / (al * be)));
         }
 #pragma unroll
         for (int u = 0; u < RL; ++u) {
@@ -1742,6 +1744,8 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             rotated = 0;
             maxr = 0u;
         }
+        my_max = 0.0f;
+        my_rot = false;
         __syncthreads();
         for (int step = 0; step < ne; step += 2) {
             rotate(ax, bx, av, bv, ia, ib, false);
@@ -1778,6 +1782,11 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             }
             __syncthreads();
         }
+        if (l16 == 0 && my_rot) {
+            rotated = 1;
+            atomicMax(&maxr, __float_as_uint(my_max));
+        }
+        __syncthreads();
         // done when no pair rotated, or when every rotation of this sweep was
         // below 1e-10 (then the pairs are orthogonal to ~1e-20 after it, below
         // the rotation threshold, and a further sweep would rotate nothing)
