@@ -1694,8 +1694,11 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
         if (!(p < P && (!odd || p < P - 1))) return;
         double c = 1.0, sn = 0.0;
         if (ga != 0.0 && al > noise2 && be > noise2 && ga * ga > tol2 * (al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = d / g2,
+            // numerator and denominator scaled by |g2|: one division fewer
+            const double d = be - al, g2 = 2.0 * ga;
+            const double sg = (d == 0.0 || ((d > 0.0) == (g2 > 0.0))) ? 1.0 : -1.0;
+            const double t = sg * fabs(g2) / (fabs(d) + sqrt(d * d + g2 * g2));
             c = 1.0 / sqrt(1.0 + t * t);
             sn = c * t;
             my_rot = true;
