@@ -25,7 +25,7 @@ Test infrastructure only (FP64, CPU).  Follows Sec. III of the paper:
     rho_eff = C1 C2 C3 C4 / Tr(C1 C2 C3 C4).
 
 The figures that fix the wiring are not part of the text; the wiring below is
-the reading stated in the design notes ("nested" placement of A, O, conj(A)
+one reading of them, stated here in full ("nested" placement of A, O, conj(A)
 along the anti-diagonal of the unit cell).  In that placement the bonds of the
 left edge chain carry, besides the environment bond chi,
     bk (T^bra -> next T^ket, also every corner leg):  A.d, O.d, B.d

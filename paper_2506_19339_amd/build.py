@@ -14,7 +14,8 @@ ARCH = "gfx950"
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", "--offload-arch=" + ARCH,
-    # no packed FP32 instructions in any HIP code (see DESIGN notes)
+    # no packed FP32 instructions in any HIP code: some of their forms have
+    # given wrong results on gfx950 without any error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
