@@ -144,6 +144,14 @@ def test_tiled_permute_of_the_move(lib, li, lo, dims, tiled):
     assert _permute_case(lib, dims, axes, 3) == tiled
 
 
+def test_tiled_permute_at_the_workload_size(lib):
+    """The largest transposition of a D = 5, chi = 100 move (50 M elements,
+    400 MB) in the tiled form, bit-exact against numpy."""
+    li, lo, dims = "vqurkzsbe", "urkzsevqb", (5, 2, 2, 2, 100, 5, 5, 5, 100)
+    axes = tuple(li.index(c) for c in lo)
+    assert _permute_case(lib, dims, axes, 5) == 1
+
+
 def test_random_permutes_tiled_and_elementwise(lib):
     """120 random permutations (rank 1-9, dims from a pool with ragged sizes,
     up to 1.5e6 elements): bit-exact against numpy in both forms; at least a
