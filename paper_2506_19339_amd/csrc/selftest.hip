@@ -3,6 +3,9 @@
 // checked in isolation.  Built into libctm_selftest.so, not into libctm.so.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "kernels.h"
 #include "perm_plan.h"
 
@@ -122,6 +125,96 @@ int ctm_selftest_permute_tiled(int rank, const long long* dims, const int* axes)
     }
     ctmk::PermTile t{};
     return ctmk::plan_perm_tile(rank, od, is, t) ? 1 : 0;
+}
+
+// Host check of the tiled permute's plan and index arithmetic (no device
+// work): the tile loop of permute_tile_kernel replayed on the host for
+// transpose(dims, axes) of in[i] = i, against the element-wise definition.
+// Returns 1 when the plan takes the tiled form and every output element is
+// written once with the right value, 0 when the plan keeps the element-wise
+// form, -1 on a mismatch, -2 when a tile exceeds the kernel's LDS buffer.
+int ctm_selftest_permute_tile_check(int rank, const long long* dims, const int* axes)
+{
+    int64_t n = 1, stride[12], od[12], is[12];
+    for (int k = rank - 1; k >= 0; --k) {
+        stride[k] = n;
+        n *= dims[k];
+    }
+    for (int k = 0; k < rank; ++k) {
+        od[k] = dims[axes[k]];
+        is[k] = stride[axes[k]];
+    }
+    ctmk::PermTile t{};
+    if (!ctmk::plan_perm_tile(rank, od, is, t)) return 0;
+    auto fdiv = [](uint32_t x, const ctmk::FastDiv& f) {
+        return (uint32_t)(((((uint64_t)x * f.mul) >> 32) + x) >> f.shr);
+    };
+    std::vector<double> out((size_t)n, -1.0), buf(ctmk::kPermTileElems + ctmk::kPermTileSide + 1);
+    std::vector<uint32_t> itab(ctmk::kPermTileSide), otab(ctmk::kPermTileSide);
+    const int U = t.U, P = (t.TI * t.U) | 1;
+    for (uint32_t tile = 0; tile < (uint32_t)t.tiles; ++tile) {
+        uint32_t r = fdiv(tile, t.fco);
+        const int co = (int)(tile - r * t.fco.d);
+        const uint32_t r2 = fdiv(r, t.fci);
+        const int ci = (int)(r - r2 * t.fci.d);
+        r = r2;
+        uint32_t ib = 0, ob = 0;
+        for (int k = 0; k < t.nrest; ++k) {
+            const uint32_t q = fdiv(r, t.rest_d[k]);
+            const uint32_t c = r - q * t.rest_d[k].d;
+            r = q;
+            ib += c * (uint32_t)t.rest_is[k];
+            ob += c * (uint32_t)t.rest_os[k];
+        }
+        const int i0 = ci * t.TI, o0 = co * t.TO;
+        const int ti = std::min(t.TI, t.Lin - i0), to = std::min(t.TO, t.Lout - o0);
+        const ctmk::FastDiv& fr = t.frun[ci == t.nci - 1 ? 1 : 0];
+        const ctmk::FastDiv& fo = t.fruno[co == t.nco - 1 ? 1 : 0];
+        if ((int)fr.d != ti * U || (int)fo.d != to * U || to * P > (int)buf.size()) return -2;
+        for (int o = 0; o < to; ++o) {
+            uint32_t x = (uint32_t)(o0 + o), off = 0;
+            for (int k = 0; k < t.nout; ++k) {
+                const uint32_t q = x / (uint32_t)t.out_d[k];
+                off += (x - q * (uint32_t)t.out_d[k]) * (uint32_t)t.out_is[k];
+                x = q;
+            }
+            itab[o] = off;
+        }
+        for (int i = 0; i < ti; ++i) {
+            uint32_t x = (uint32_t)(i0 + i), off = 0;
+            for (int k = 0; k < t.nin; ++k) {
+                const uint32_t q = x / (uint32_t)t.in_d[k];
+                off += (x - q * (uint32_t)t.in_d[k]) * (uint32_t)t.in_os[k];
+                x = q;
+            }
+            otab[i] = off;
+        }
+        const int run = (int)fr.d;
+        const uint32_t ibase = ib + (uint32_t)i0 * (uint32_t)U;
+        for (int e = 0; e < to * run; ++e) {
+            const int o = (int)fdiv((uint32_t)e, fr);
+            buf[o * P + (e - o * run)] = (double)(ibase + itab[o] + (uint32_t)(e - o * run));
+        }
+        const int runo = (int)fo.d;
+        const uint32_t obase = ob + (uint32_t)o0 * (uint32_t)U;
+        for (int e = 0; e < ti * runo; ++e) {
+            const int i = (int)fdiv((uint32_t)e, fo);
+            const int w = e - i * runo;
+            const int o = (int)fdiv((uint32_t)w, t.fU);
+            const uint32_t dst = obase + otab[i] + (uint32_t)w;
+            if ((int64_t)dst >= n || out[dst] != -1.0) return -1;
+            out[dst] = buf[o * P + i * U + (w - o * U)];
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t rem = i, off = 0;
+        for (int k = rank - 1; k >= 0; --k) {
+            off += (rem % od[k]) * is[k];
+            rem /= od[k];
+        }
+        if (out[i] != (double)off) return -1;
+    }
+    return 1;
 }
 
 // out = transpose(in, axes): in has dims[0..rank-1] (row-major), out axis k is
