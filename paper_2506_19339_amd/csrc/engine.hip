@@ -679,8 +679,6 @@ struct Worker {
             for (size_t i = b0; i < b1; ++i) {
                 JReq& r = rq[i];
                 REQUIRE(r.n <= 1024, "Jacobi: too many columns");
-                Tn X = tmp({r.n, r.m});
-                ctmk::copy(st, r.X, X.p, r.m * r.n);
                 Tn W = tmp({r.n, r.n});
                 r.U = tmp({r.n, r.m});
                 r.V = tmp({r.n, r.n});
@@ -691,9 +689,17 @@ struct Worker {
                     sw = sweeps_dev + sweep_jobs.size();
                     sweep_jobs.push_back({r.m, r.n, r.want_v});
                 }
-                jb.job[jb.n++] = ctmk::JacobiJob{X.p, W.p, r.U.p, r.V.p, r.S.p, (int)r.m, (int)r.n,
-                                                 r.want_v ? 1 : 0, sw};
+                jb.job[jb.n++] = ctmk::JacobiJob{const_cast<double*>(r.X), W.p, r.U.p, r.V.p, r.S.p, (int)r.m,
+                                                 (int)r.n, r.want_v ? 1 : 0, sw};
             }
+            // the kernels for larger problems rotate X in place: they get copies
+            if (!ctmk::jacobi_reads_only(jb))
+                for (int t = 0; t < jb.n; ++t) {
+                    ctmk::JacobiJob& j = jb.job[t];
+                    Tn X = tmp({(int64_t)j.n, (int64_t)j.m});
+                    ctmk::copy(st, j.X, X.p, (int64_t)j.m * j.n);
+                    j.X = X.p;
+                }
             hipEvent_t e = prof_begin();
             ctmk::jacobi_svd(st, jb, kJacobiSweeps);
             prof_end(1, e, 0.0);

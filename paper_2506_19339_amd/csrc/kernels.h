@@ -12,7 +12,7 @@ struct PermDesc {
 };
 
 struct JacobiJob {
-    double* X;  // m x n column-major input (destroyed)
+    double* X;  // m x n column-major input (destroyed, unless jacobi_reads_only)
     double* W;  // n x n workspace
     double* U;  // m x n column-major output
     double* V;  // n x n column-major output
@@ -98,6 +98,8 @@ void spectrum_delta(hipStream_t s, double* sv, int n, const double* trace, doubl
 void trace(hipStream_t s, const double* X, int n, double* out);
 void finite_check(hipStream_t s, const double* x, int64_t n, int* flag);
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps);
+// true when jacobi_svd leaves every job's X unchanged (register kernel)
+bool jacobi_reads_only(const JacobiBatch& jobs);
 void cholqr(hipStream_t s, const CholBatch& jobs, double shift);
 // negate row i of UT (rows x m) and VT (rows x n) when UT's largest-magnitude
 // entry in that row is negative

@@ -1844,6 +1844,20 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
     }
 }
 
+// the register kernel takes every job of the batch (m, n <= kSmallJacobi and
+// one want_v for all); it reads X and never writes it
+bool jacobi_reads_only(const JacobiBatch& jobs)
+{
+    bool small = jobs.n > 0, any_v = false, all_v = true;
+    for (int i = 0; i < jobs.n; ++i) {
+        const JacobiJob& j = jobs.job[i];
+        small = small && j.m <= kSmallJacobi && j.n <= kSmallJacobi;
+        any_v = any_v || j.want_v;
+        all_v = all_v && j.want_v;
+    }
+    return small && (all_v || !any_v);
+}
+
 void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
 {
     if (jobs.n <= 0) return;
@@ -1864,7 +1878,7 @@ void jacobi_svd(hipStream_t s, const JacobiBatch& jobs, int max_sweeps)
         any_v = any_v || jobs.job[i].want_v;
         all_v = all_v && jobs.job[i].want_v;
     }
-    if (small && (all_v || !any_v)) {
+    if (jacobi_reads_only(jobs)) {
         if (all_v)
             hipLaunchKernelGGL((jacobi_reg_kernel<true>), dim3(jobs.n), dim3(kRegThreads), 0, s, jobs, max_sweeps);
         else
