@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--no-reduced-leg", action="store_true")
     ap.add_argument("--no-lbfgs-leg", action="store_true")
     ap.add_argument("--lbfgs-steps", type=int, default=5)
+    ap.add_argument("--no-serving-leg", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving trace replayed in real time (Poisson, 20/s)")
     ap.add_argument("--reduced-only", action="store_true",
                     help="only time the reduced method on the workload (for profiling it alone)")
     ap.add_argument("--method-sweep", action="store_true",
@@ -301,6 +304,29 @@ def main():
                      moves_per_eval=r.moves / r.evaluations, cold_moves=r.history[0][3],
                      f_start=r.history[0][1], f_end=r.f, g_inf_start=r.history[0][2], g_inf_end=r.g_inf)
 
+    serving = None
+    if not args.no_serving_leg:
+        # the serving form: the seeded Poisson trace (mean 20 requests/s,
+        # beta ~ U[0.18, 0.26], D in {2,3,4,5}, chi in {16,32,64,100,128},
+        # f + grad each) replayed in real time with continuous batching
+        from paper_2506_19339_amd import serving
+        print("serving leg", file=sys.stderr, flush=True)
+        reqs = serving.trace_requests(args.serving_requests, 20.0, 1)
+        srv = serving.Server(hbm_budget=200 * serving.GiB, max_slots=16)
+        done = [0]
+
+        def progress(req):
+            done[0] += 1
+            if done[0] % 16 == 0:
+                print("served %d / %d" % (done[0], len(reqs)), file=sys.stderr, flush=True)
+
+        st = srv.run(reqs, realtime=True, on_done=progress)
+        srv.close()
+        serving = st.summary()
+        serving["trace"] = "%d requests, Poisson arrivals at 20/s (seed 1), tol 1e-9, max_iter 200" % len(reqs)
+        serving["failed"] = sum(1 for r in reqs if r.status not in (0, ctm.CTM_ENOCONV))
+        serving["not_converged"] = sum(1 for r in reqs if r.status == ctm.CTM_ENOCONV)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -338,6 +364,7 @@ def main():
         "fp32_form": fp32,
         "reduced_method": reduced,
         "lbfgs": lbfgs,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

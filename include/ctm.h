@@ -95,6 +95,17 @@ typedef enum {
  * otherwise).  Device memory grows as chi^2 (D^2 d)^2 for the enlarged
  * corner and (D^2 d)^4 for a. */
 #define CTM_FLAG_REDUCED 4
+/* CTM_FLAG_FULL_P4: build the second-stage projector of the cell-boundary bond
+ * (projector 4) from the full 2x2 block of enlarged corners, vertical legs
+ * renormalised by projector 1 and its right-move image, horizontal legs whole
+ * (Appendix, Fig. Projector4(a); O(chi^3 D^4 d^3)).  Default: the half
+ * construction of the main text from the two left enlarged corners, their
+ * horizontal legs renormalised by the up / down images of projector 1
+ * (Fig. Projector4(b); O(chi^3 D^3 d^3)).  The full construction's
+ * rho_B rho_T is a product of four corners, whose spectrum decays as the
+ * square of the half one's: the same svd_cutoff keeps fewer directions.
+ * Split-CTMRG only. */
+#define CTM_FLAG_FULL_P4 8
 
 typedef struct {
     int D;              /* PEPS virtual bond dimension, 1 <= D <= 8               */

@@ -15,14 +15,35 @@ Test infrastructure only (FP64, CPU).  Follows Sec. III of the paper:
   * Sec. III C, Eqs. (projector construction, ... 2): rho_B rho_T = U S V,
     keep chi, P_B = rho_T V^+ (S^1/2)^+, P_T = (S^1/2)^+ U^+ rho_B.
   * Appendix, six-projector scheme: P2, P3 from a 1x1 unit cell with its full
-    environment; P1 from a one-column, two-row strip; half P4 from the two
-    enlarged corners of a 2x1 block whose bra legs are pre-renormalised by P1
-    and its up / down images; P5, P6 from a two-column, one-row block
+    environment; P1 from a one-column, two-row strip; P4 from the enlarged
+    corners with their bra legs pre-renormalised by P1: by default the half
+    construction of the main text (the two left corners of a 2x1 block,
+    Fig. Projector4(b), horizontal legs renormalised by the up / down images
+    of P1), optionally the full one (2x2 block, Fig. Projector4(a): vertical
+    legs renormalised by P1 and its right-move image P1^R = (P1B, P1T),
+    horizontal legs whole); P5, P6 from a two-column, one-row block
     pre-renormalised by P2, P2^R (resp. P3, P3^R).  In the D2 scheme
     P2^R_T = P3_B, P2^R_B = P3_T, P3^R_T = P2_B, P3^R_B = P2_T, and the up / down
-    images of P1 are its transposes.
+    images of P1 are its transposes.  The full P4's rho_B rho_T is a product
+    of four enlarged corners: its spectrum decays as the square of the half
+    one's, so the same relative cutoff truncates it to fewer directions (with
+    1e-12 it reaches the reduced value on tensors where the half construction
+    does not settle, e.g. the norm network of D = 3, seed 8 at chi = 27).
+  * Sec. III C, environment selection: the rank of rho_B rho_T is bounded by
+    the corner matrices of its patch.  During the growth phase (the corner
+    bond still below chi after the product boundary) a rank-deficient
+    rho_B rho_T would cut a bond below chi for want of environment, not of
+    weight; such a pair is replaced by the orthogonal projector onto the
+    leading eigenvectors of the truncated legs' Gram matrix (projector_pair).
   * Sec. III D: convergence from the singular values of
     rho_eff = C1 C2 C3 C4 / Tr(C1 C2 C3 C4).
+
+Domain of this reading: networks whose transfer matrix has a unique leading
+eigenvalue.  On period-2 ordered networks (a degenerate +-lambda leading
+pair, oracle.unsplit.leading_pair_degenerate) a one-site environment can
+only hold a mixture of the two ordered boundaries; the D2 split iteration
+then has several fixed points and, from the product boundary, may settle on
+one whose kappa is not the reduced method's.
 
 The figures that fix the wiring are not part of the text; the wiring below is
 one reading of them, stated here in full ("nested" placement of A, O, conj(A)
@@ -54,6 +75,7 @@ def ein(spec, *ops):
 from . import model
 
 SVD_CUTOFF = 1e-12
+RANK_BAND = 10.0     # hysteresis band of the kept rank (kept_rank)
 GROW_CHI = 1 << 30   # "no truncation" for the first move
 LAST_STAGE2_ENVS = {}  # rho_T / rho_B of P5 and P6 from the last stage2 call
 
@@ -83,14 +105,49 @@ def right_edge(env):
 # projector construction (Eqs. projector construction / ... 2)
 # ----------------------------------------------------------------------------
 
-def projector_pair(rhoB, rhoT, chi, cutoff=SVD_CUTOFF):
+def kept_rank(S, chi, cutoff, prev=None):
+    """Number of singular values kept: those above cutoff * S[0], at most chi.
+    With the bond's previous count prev (same projector slot, last move) the
+    count only moves when a value leaves the band cutoff ... cutoff * RANK_BAND:
+    prev is clamped between the counts above the band's upper and lower edges
+    (a value that fell below the cutoff comes back only above
+    cutoff * RANK_BAND).  Without the band a value sitting at the cutoff is
+    kept and dropped on alternate moves and the iteration ends in a two-move
+    cycle (the environment never settles).  Both edges are at or above the
+    cutoff, where the GPU's factorisation resolves the singular values."""
+    s0 = S[0]
+    if prev is None:
+        k = int(np.sum(S > cutoff * s0))
+    else:
+        hi = int(np.sum(S > cutoff * RANK_BAND * s0))
+        lo = int(np.sum(S > cutoff * s0))
+        k = min(max(prev, hi), lo)
+    return max(1, min(chi, k))
+
+
+def projector_pair(rhoB, rhoT, chi, cutoff=SVD_CUTOFF, fill=False, prev=None):
     """rhoT: (trunc x remT) matrix, rhoB: (remB x trunc) matrix.
     Returns (PT [k x trunc], PB [trunc x k], kept singular values).
 
     A bond whose untruncated dimension does not exceed chi is not truncated:
-    both projectors are the identity.  This keeps the corner bonds at least as
-    large as the bonds being truncated once truncation starts (Sec. III C,
-    environment-selection principle) and makes the growth phase exact."""
+    both projectors are the identity.  Otherwise rho_B rho_T = U S V, the
+    chi leading triplets above the relative cutoff are kept and
+    PB = rhoT V^T S^-1/2, PT = S^-1/2 U^T rhoB (Eqs. projector construction).
+
+    fill (growth phase, Sec. III C environment-selection principle): the
+    number of non-zero singular values of rho_B rho_T is bounded by the rank
+    of the corner matrices of the patch.  While the environment's corner bond
+    is still below chi (the first truncated moves after the product
+    boundary), that bound reflects the small environment, not the network.
+    If rho_B rho_T then has fewer than k = min(chi, trunc) singular values
+    above the cutoff, the pair is the orthogonal projector onto the leading
+    left singular vectors of Z = [rhoT / |rhoT|, rhoB^T / |rhoB|] (the
+    eigenvectors of the truncated legs' Gram matrix
+    G = rhoT rhoT^T / |rhoT|^2 + rhoB^T rhoB / |rhoB|^2): at most k of them,
+    those whose singular value is above the same relative cutoff.  So no bond
+    is cut below chi on the strength of a rank-deficient environment, and
+    directions that neither half reaches are dropped.  Returned singular
+    values are then empty."""
     ntr = rhoT.shape[0]
     if ntr <= chi:
         eye = np.eye(ntr)
@@ -100,7 +157,14 @@ def projector_pair(rhoB, rhoT, chi, cutoff=SVD_CUTOFF):
     if S.size == 0 or S[0] <= 0:
         raise FloatingPointError("zero rho_B rho_T")
     keep = int(np.sum(S > cutoff * S[0]))
-    keep = max(1, min(chi, keep))
+    k = min(chi, ntr)
+    if fill and keep < k:
+        Z = np.concatenate([rhoT / np.linalg.norm(rhoT), rhoB.T / np.linalg.norm(rhoB)], axis=1)
+        Uz, sz, _ = np.linalg.svd(Z, full_matrices=False)
+        kf = max(1, min(k, int(np.sum(sz > cutoff * sz[0]))))
+        Q = Uz[:, :kf]
+        return Q.T.copy(), Q.copy(), np.zeros(0)
+    keep = kept_rank(S, chi, cutoff, prev)
     sinv = 1.0 / np.sqrt(S[:keep])
     PB = (rhoT @ Vh[:keep].T) * sinv[None, :]
     PT = sinv[:, None] * (U[:, :keep].T @ rhoB)
@@ -191,21 +255,26 @@ def B_of(A):
 # stage 1: P1, P2, P3
 # ----------------------------------------------------------------------------
 
-def stage1(env, A, O, chi, cutoff=SVD_CUTOFF):
+def _prev(env, slot):
+    r = env.get("ranks")
+    return None if r is None else r[slot]
+
+
+def stage1(env, A, O, chi, cutoff=SVD_CUTOFF, fill=False):
     up_ki, up_ib, up_bk = upper_sequence(env, A, O)
     lo_ki, lo_ib, lo_bk = lower_sequence(env, A, O)
     # P1: trunc (chi, B) ; rem (A, O, chiR)
     rT = _mat(up_bk.transpose(0, 1, 3, 2, 4), 2)                # (tbb,Bd) x (Ad,Od,rbb)
     rB = _mat(lo_bk.transpose(1, 2, 4, 0, 3), 3)                # (Au,Ou,rka) x (tka,Bu)
-    P1 = projector_pair(rB, rT, chi, cutoff)
+    P1 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 0))
     # P2: trunc (chi, O, B) ; rem (A, p, chiR)
     rT = _mat(up_ki.transpose(0, 3, 4, 2, 1, 5), 3)             # (tkb,Ou,Bu) x (Ad,p,rkb)
     rB = _mat(lo_ki.transpose(4, 1, 5, 0, 2, 3), 3)             # (Ad,p,ria) x (tia,Ou,Bu)
-    P2 = projector_pair(rB, rT, chi, cutoff)
+    P2 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 1))
     # P3: trunc (chi, B, q) ; rem (A, O, chiR)
     rT = _mat(up_ib.transpose(0, 4, 1, 3, 2, 5), 3)             # (tib,Bu,q) x (Ad,Od,rib)
     rB = _mat(lo_ib.transpose(3, 4, 5, 0, 2, 1), 3)             # (Ad,Od,rba) x (tba,Bu,q)
-    P3 = projector_pair(rB, rT, chi, cutoff)
+    P3 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 2))
     return P1, P2, P3
 
 
@@ -270,7 +339,7 @@ def enlarged_C4(env, A, O):
 # stage 2: P4 (half), P5, P6
 # ----------------------------------------------------------------------------
 
-def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
+def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF, fill=False, p4="half"):
     D, d, P = A.shape[1], O.shape[2], A.shape[0]
     Tk, Ti, Tb = env["Tk"], env["Ti"], env["Tb"]
     Rk, Ri, Rb = right_edge(env)
@@ -288,9 +357,27 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
     C4p = ein("cvwrhiy,vrX->cwhXyi", K4, P1B)             # right (s3, Ar) -> X
     # C4p [c_u, Au, Ou, c_r', Br, Or]
     nT = C1p.shape[0] * D * d
-    rT = C1p.reshape(nT, -1)                                    # (c_d,Ad,Od) x (c_r,Ar,Or)
-    rB = C4p.reshape(nT, -1).T                                  # (c_r',Br,Or) x (c_u,Au,Ou)
-    P4 = projector_pair(rB, rT, chi, cutoff)
+    if p4 == "full":
+        # full projector 4 (Appendix, Fig. Projector4(a)): the 2x2 block of
+        # enlarged corners, vertical legs after P1 (left bond) and its
+        # right-move image P1^R = (P1B, P1T) (right bond), horizontal legs whole.
+        # K1 (P1T on the down leg): [u=chi right, c, r=Ar, d=Ad, e=Or, f=Od, v=Br]
+        # K4 (P1B on the up leg):   [c, s=chi right, a=Au, r=Ar, h=Ou, o=Or, y=Br]
+        # upper right corner: the diagonal-reflection image of the enlarged C4,
+        # [a0 -> left chi, s3 -> down chi, Au, Ar, Ou, Or, Bu, Br -> A.l, A.d,
+        # O.l, O.d, B.l, B.d], with P1^R_T = P1B on its down leg's (chi, A.d)
+        C2e = ein("kvwrhiuy,vrX->kwhuXiy", enlarged_C4(env, A, O), P1B)   # [chi, Al, Ol, Bl, X, Od, Bd]
+        rhoT4 = ein("ucrdefv,urevXiy->cdfXiy", K1, C2e)                 # [c, Ad, Od | X, Od2, Bd2]
+        # lower right corner: the 180-degree image of the enlarged C1 with
+        # P1^R_B = P1T on its up leg's (chi, A.u): the arrays of K1 with legs
+        # [chi left, c', B.l, B.u, O.l, O.u, A.l]
+        rhoB4 = ein("csarhoy,sCyBoOr->cahCBO", K4, K1)                  # [c, Au, Ou | C, Bu2, Ou2]
+        n4 = rhoT4.shape[0] * rhoT4.shape[1] * rhoT4.shape[2]
+        P4 = projector_pair(rhoB4.reshape(n4, -1).T, rhoT4.reshape(n4, -1), chi, cutoff, fill, _prev(env, 3))
+    else:
+        rT = C1p.reshape(nT, -1)                                # (c_d,Ad,Od) x (c_r,Ar,Or)
+        rB = C4p.reshape(nT, -1).T                              # (c_r',Br,Or) x (c_u,Au,Ou)
+        P4 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 3))
 
     # ---- P5 (ki bond, stage 2): two-column block cut at ki
     X = ein("xy,xus,sot,tbw->yuobw", C1, Tk, Ti, Tb)      # C1 + top cell 1
@@ -319,7 +406,7 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
     LR = ein("hpmsnuva,ehap->emsnuv", LR, P3T)            # [c2R,Ol2,Ou2,Bl2,Bu2,v3]
     rhoB5 = ein("epatyv,ftsyuv->eapsuf", LL, LR)          # [c2L,Ad1,p1,Ou2,Bu2,c2R]
     n5 = rhoT5.shape[0] * D * P
-    P5 = projector_pair(rhoB5.reshape(n5, -1).T, rhoT5.reshape(n5, -1), chi, cutoff)
+    P5 = projector_pair(rhoB5.reshape(n5, -1).T, rhoT5.reshape(n5, -1), chi, cutoff, fill, _prev(env, 4))
 
     # ---- P6 (ib bond, stage 2): same block cut at ib
     X = ein("xy,xus,sot,tbw->yuobw", C1, Tk, Ti, Tb)
@@ -348,7 +435,7 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
     LR6 = ein("kqnuvao,ekoa->eqnuv", LR6, P2T)            # [c3R,q2,Bl2,Bu2,v3]
     rhoB6 = ein("eyaov,fqyuv->eaouqf", LL6, LR6)          # [c3L,Ad1,Od1,Bu2,q2,c3R]
     n6 = rhoT6.shape[0] * D * d
-    P6 = projector_pair(rhoB6.reshape(n6, -1).T, rhoT6.reshape(n6, -1), chi, cutoff)
+    P6 = projector_pair(rhoB6.reshape(n6, -1).T, rhoT6.reshape(n6, -1), chi, cutoff, fill, _prev(env, 5))
     LAST_STAGE2_ENVS.clear()
     LAST_STAGE2_ENVS.update(rhoT5=rhoT5, rhoB5=rhoB5, rhoT6=rhoT6, rhoB6=rhoB6)
     return P4, P5, P6, C1p, C4p
@@ -358,11 +445,21 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF):
 # one symmetric split-CTMRG step
 # ----------------------------------------------------------------------------
 
-def step(env, A, O, chi, cutoff=SVD_CUTOFF):
+def growing(env, chi):
+    """Growth phase: the corner bond has not yet reached chi since the
+    product boundary (the environment-selection principle of Sec. III C
+    cannot hold yet)."""
+    return (not env.get("grown", False)) and env["C1"].shape[0] < chi
+
+
+def step(env, A, O, chi, cutoff=SVD_CUTOFF, p4="half"):
+    """One symmetric split-CTMRG move.  p4: "half" (the main-text choice,
+    Fig. Projector4(b)) or "full" (Fig. Projector4(a))."""
     D, d, P = A.shape[1], O.shape[2], A.shape[0]
     B = B_of(A)
-    P1, P2, P3 = stage1(env, A, O, chi, cutoff)
-    P4, P5, P6, C1p, C4p = stage2(env, A, O, chi, P1, P2, P3, cutoff)
+    fill = growing(env, chi)
+    P1, P2, P3 = stage1(env, A, O, chi, cutoff, fill)
+    P4, P5, P6, C1p, C4p = stage2(env, A, O, chi, P1, P2, P3, cutoff, fill, p4)
     c1, c2, c3 = P1[0].shape[0], P2[0].shape[0], P3[0].shape[0]
     P1T, P1B, P2T, P2B, P3T, P3B = stage1_tensors(env, A, O, P1, P2, P3)
     P4T = _as_tensor_T(P4[0], (c1, D, d))
@@ -400,6 +497,9 @@ def step(env, A, O, chi, cutoff=SVD_CUTOFF):
     new = dict(C1=C1_n, C4=C4_n, Tk=Tk_n, Ti=Ti_n, Tb=Tb_n)
     for k in new:
         new[k] = new[k] / np.linalg.norm(new[k])
+    new["grown"] = bool(env.get("grown", False) or C1_n.shape[0] >= chi)
+    # kept counts of the factorised pairs (identity and growth-phase pairs: none)
+    new["ranks"] = [P[2].size if P[2].size else None for P in (P1, P2, P3, P4, P5, P6)]
     projs = dict(P1=P1, P2=P2, P3=P3, P4=P4, P5=P5, P6=P6)
     return new, projs
 
@@ -429,7 +529,7 @@ def spectrum_delta(s_new, s_old):
     return float(np.linalg.norm(a - b))
 
 
-def run(A, O, chi, max_iter, tol=0.0, cutoff=SVD_CUTOFF, env=None):
+def run(A, O, chi, max_iter, tol=0.0, cutoff=SVD_CUTOFF, env=None, p4="half"):
     D, d = A.shape[1], O.shape[2]
     if env is None:
         env = init_env(D, d)
@@ -440,7 +540,7 @@ def run(A, O, chi, max_iter, tol=0.0, cutoff=SVD_CUTOFF, env=None):
         # the first move from the product boundary never truncates: its
         # projector environments would see the boundary vectors only and would
         # cap the rank of every bond that carries lines of the row above
-        env, _ = step(env, A, O, chi if it > 1 else GROW_CHI, cutoff)
+        env, _ = step(env, A, O, chi if it > 1 else GROW_CHI, cutoff, p4)
         s = corner_spectrum(env)
         delta = spectrum_delta(s, s_old)
         history.append(delta)
@@ -565,11 +665,11 @@ def bra_environment(env, A, O):
     return ein("qtgbnwvz,wgtez->qnbve", X, bot)
 
 
-def free_energy(beta, A, chi, max_iter, tol=0.0, cutoff=SVD_CUTOFF):
+def free_energy(beta, A, chi, max_iter, tol=0.0, cutoff=SVD_CUTOFF, p4="half"):
     O3 = model.pepo_O(beta)
     O2 = model.identity_pepo()
-    env3, it3, dl3, h3 = run(A, O3, chi, max_iter, tol, cutoff)
-    env2, it2, dl2, h2 = run(A, O2, chi, max_iter, tol, cutoff)
+    env3, it3, dl3, h3 = run(A, O3, chi, max_iter, tol, cutoff, p4=p4)
+    env2, it2, dl2, h2 = run(A, O2, chi, max_iter, tol, cutoff, p4=p4)
     lk3, _ = log_kappa(env3, A, O3)
     lk2, _ = log_kappa(env2, A, O2)
     f = -(lk3 - lk2) / beta
@@ -590,6 +690,6 @@ def gradient(beta, A, info):
     return model.d4_symmetrize(g)
 
 
-def f_and_grad(beta, A, chi, max_iter, tol=0.0, cutoff=SVD_CUTOFF):
-    f, info = free_energy(beta, A, chi, max_iter, tol, cutoff)
+def f_and_grad(beta, A, chi, max_iter, tol=0.0, cutoff=SVD_CUTOFF, p4="half"):
+    f, info = free_energy(beta, A, chi, max_iter, tol, cutoff, p4)
     return f, gradient(beta, A, info), info

@@ -92,6 +92,17 @@ def corner_spectrum(C):
     return s / np.sum(s)
 
 
+def leading_pair_degenerate(C, rel=1e-4):
+    """True when the two largest |eigenvalues| of the converged symmetric corner
+    agree to rel: the network's transfer matrix then has a (near-)degenerate
+    leading pair +-lambda, i.e. the network is period-2 ordered (a staggered
+    fixed point that a one-site environment represents only as a mixture of
+    the two ordered boundaries)."""
+    ev = np.linalg.eigvalsh(0.5 * (C + C.T))
+    ev = np.sort(np.abs(ev))[::-1]
+    return ev.size > 1 and ev[0] - ev[1] <= rel * ev[0]
+
+
 def spectrum_delta(s_new, s_old):
     n = max(s_new.size, s_old.size)
     a = np.zeros(n)

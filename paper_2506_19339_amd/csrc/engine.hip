@@ -157,6 +157,9 @@ struct Net {
     double* O = nullptr;             // [2][2][d][d][d][d]
     double *C1 = nullptr, *C4 = nullptr, *Tk = nullptr, *Ti = nullptr, *Tb = nullptr;
     int64_t xbk = 1, xki = 1, xib = 1;
+    // the corner bond has reached chi since the product boundary; before that
+    // (growth phase) rank-deficient projector environments are not trusted
+    bool grown = false;
     double* s_old = nullptr;         // previous normalised spectrum
     int* n_old = nullptr;
     double* delta = nullptr;         // last spectrum change
@@ -185,6 +188,13 @@ constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resid
 constexpr int kOversample = 16;
 constexpr int kWarmPowerIters = 2;  // power steps when every subspace starts from last move's basis
                                     // (the iteration continues across moves)
+constexpr int kColdPowerIters = 10; // power steps from random normals
+// the same when the Rayleigh-Ritz core is less than 1.25 kk wide (kk > 112):
+// at D = 6, chi = 144 (core 160) ten cold steps resolve the early moves'
+// projectors to ~1e-6 only (f 2e-5 off the oracle after six moves), forty to
+// rounding
+constexpr int kColdPowerItersThin = 40;
+constexpr int kWarmPowerItersThin = 8;
 constexpr double kWarmGate = 1e-3;  // spectrum change per move below which the last bases are reused
 constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resident Jacobi)
 // relative pseudo-inverse cutoff of S^1/2: singular values of rho_B rho_T below
@@ -192,7 +202,13 @@ constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resi
 // spectrum in its Gram steps, so 1e-8 is the smallest relative singular value
 // it resolves in FP64.
 constexpr double kDefaultCutoff = 1e-8;
+// hysteresis band of a projector slot's kept count: it stays at last move's
+// value while that lies between the counts above cutoff * band and cutoff (a
+// value sitting at the cutoff otherwise enters and leaves on alternate moves
+// and the environment cycles)
+constexpr double kRankBand = 10.0;
 constexpr int kJacobiSweeps = 40;
+constexpr int kFillPowerIters = 40; // power steps of the growth-phase Gram factorisations
 constexpr int kMaxBatch = 16;       // projectors factorised together
 constexpr int kMaxIterateBatch = 64; // contexts advanced by one ctm_iterate_batch call
 // spectrum-change floors of the reduced-precision phases (rounding noise of
@@ -226,6 +242,7 @@ struct Worker {
     double* part = nullptr;          // reduction partials
     double* scal = nullptr;          // scratch scalars
     int* icount = nullptr;           // device ints for rank read-back
+    int prev_rank[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // last kept count per projector slot (-1: none)
     double* gws = nullptr;           // split-K partial products of the GEMMs
     int64_t gws_cap = 0;
     uint64_t svd_calls = 0;
@@ -236,6 +253,7 @@ struct Worker {
     bool trace_sweeps = false;       // testing aid: log the sweeps of every Jacobi job (profile mode)
     bool warm_starts = true;         // keep each slot's Ritz basis for the next move
     bool reduced = false;            // reduced (unsplit) C4v CTMRG on the fused site tensor
+    bool full_p4 = false;            // projector 4 from the 2x2 block (default: the half construction)
     double last_delta = 1.0;         // spectrum change of this network's last move (host copy)
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
     double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
@@ -257,6 +275,7 @@ struct Worker {
         A = a;
         profiling = (c.flags & CTM_FLAG_PROFILE) != 0;
         reduced = (c.flags & CTM_FLAG_REDUCED) != 0;
+        full_p4 = (c.flags & CTM_FLAG_FULL_P4) != 0;
         // the reduced method's enlarged corner (chi D^2 d wide, cut in a flat
         // part of its spectrum) needs the full power iteration every move: with
         // two warm steps its spectrum change stalls near 1e-7 (D = 5, chi = 100)
@@ -266,7 +285,7 @@ struct Worker {
         HIPCHK(hipEventCreateWithFlags(&ev_side_done, hipEventDisableTiming));
         part = keep(ctmk::kRedBlocks);
         scal = keep(16);
-        icount = (int*)keep(kMaxBatch);
+        icount = (int*)keep(2 * kMaxBatch);
         gws_cap = (int64_t)1 << 22;   // 32 MiB
         gws = keep(gws_cap);
         if (profiling) sweeps_dev = (int*)keep(kSweepSlots / 2);
@@ -765,7 +784,8 @@ struct Worker {
         bool valid = false;
     };
     Warm warm[6];
-    void svd_batch(std::vector<SvdReq>& rq)
+    // power: power steps of the subspace iteration (0: the schedule below)
+    void svd_batch(std::vector<SvdReq>& rq, int power = 0)
     {
         Prec fp64(*this, CTM_FP64);   // factorisations stay FP64 in every precision form
         std::vector<JReq> ex;
@@ -837,7 +857,16 @@ struct Worker {
         // inside the power steps one Cholesky-QR pass keeps the basis well
         // conditioned; the bases that enter the Rayleigh-Ritz core (last P, Q)
         // get the second pass that makes them orthonormal
-        const int q = cfg.power_iters > 0 ? cfg.power_iters : (all_warm ? kWarmPowerIters : 10);
+        // with little oversampling (core narrower than 1.25 kk: the core is
+        // capped at 128 + the 16 oversampling vectors only when kk > 112) the
+        // kept space converges as (sigma_k / sigma_kk)^q over a flat spectrum
+        // near the cut, so such batches get more steps
+        bool thin = false;
+        for (size_t j = 0; j < nr; ++j) thin = thin || 4 * Pt[j].d[0] < 5 * rq[rnd[j]].kk;
+        const int q = power > 0 ? power
+                    : (cfg.power_iters > 0 ? cfg.power_iters
+                                           : (all_warm ? (thin ? kWarmPowerItersThin : kWarmPowerIters)
+                                                       : (thin ? kColdPowerItersThin : kColdPowerIters)));
         std::vector<Tn> Ms(nr);
         for (size_t j = 0; j < nr; ++j) Ms[j] = rq[rnd[j]].M;
         // a whole last-move Ritz basis has orthonormal rows already
@@ -895,7 +924,12 @@ struct Worker {
     // projector pairs from (rhoT (t x rT), rhoB (rB x t)) for every entry of
     // the list; the factorisations of all entries share their launches and one
     // read-back of the kept ranks.
-    std::vector<Projector> projectors(const std::vector<std::pair<Tn, Tn>>& prs, int64_t chi, int slot0)
+    // fill (growth phase, environment-selection principle): an entry whose
+    // rho_B rho_T has fewer than min(chi, t) singular values above the cutoff
+    // gets the orthogonal pair PT = Q^T, PB = Q instead, Q the min(chi, t)
+    // leading eigenvectors of G = rhoT rhoT^T / |rhoT|^2 + rhoB^T rhoB / |rhoB|^2
+    std::vector<Projector> projectors(const std::vector<std::pair<Tn, Tn>>& prs, int64_t chi, int slot0,
+                                      bool fill = false)
     {
         REQUIRE(prs.size() <= (size_t)kMaxBatch, "too many projectors in one batch");
         std::vector<Projector> out(prs.size());
@@ -934,17 +968,76 @@ struct Worker {
         // order the unit roundoff; singular values below that level are noise
         if (bulk == CTM_FP32) cut = std::max(cut, lp_cut > 0 ? lp_cut : kLpCutFp32);
         if (bulk == CTM_BF16) cut = std::max(cut, lp_cut > 0 ? lp_cut : kLpCutBf16);
-        for (size_t j = 0; j < rq.size(); ++j) ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut, icount + j);
-        int rank[kMaxBatch] = {0};
-        HIPCHK(hipMemcpyAsync(rank, icount, rq.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        // counts above cut (plain rule) and above cut * band: a slot's kept
+        // count stays at last move's value while that lies between the two
+        // (the hysteresis of the oracle's split.kept_rank)
+        const size_t nq = rq.size();
+        for (size_t j = 0; j < nq; ++j) {
+            ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut, icount + j);
+            ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut * kRankBand, icount + nq + j);
+        }
+        int cnt[2 * kMaxBatch] = {0};
+        HIPCHK(hipMemcpyAsync(cnt, icount, 2 * nq * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        int rank[kMaxBatch] = {0};
+        for (size_t j = 0; j < nq; ++j) {
+            const int prev = (rq[j].slot >= 0 && rq[j].slot < 8) ? prev_rank[rq[j].slot] : -1;
+            rank[j] = prev < 0 ? cnt[j] : std::min(std::max(prev, cnt[nq + j]), cnt[j]);
+        }
         // P_B = rho_T V S^-1/2 and P_T = S^-1/2 U^T rho_B amplify the directions
         // of small singular values: FP64 in every form
         Prec fp64(*this, CTM_FP64);
+        std::vector<SvdReq> fq;
+        std::vector<int> fill_of(rq.size(), -1);
+        int frank[kMaxBatch] = {0};
+        if (fill) {
+            for (size_t j = 0; j < rq.size(); ++j) {
+                const Tn &rT = prs[of[j]].first, &rB = prs[of[j]].second;
+                const int64_t t = rT.d[0], remT = rT.d[1], remB = rB.d[0], k = std::min<int64_t>(chi, t);
+                if (rank[j] >= k) continue;
+                // Z^T = [rhoT^T / |rhoT| ; rhoB / |rhoB|]  ((remT + remB) x t): its right
+                // singular vectors are the leading eigenvectors of the Gram matrix
+                Tn Zt = tmp({remT + remB, t});
+                Tn rTt = perm(rT, "ab->ba");
+                ctmk::copy(st, rTt.p, Zt.p, remT * t);
+                ctmk::copy(st, rB.p, Zt.p + remT * t, remB * t);
+                Tn nrm = tmp({2});
+                ctmk::dot(st, rT.p, rT.p, rT.n(), nrm.p, part, 1);
+                ctmk::dot(st, rB.p, rB.p, rB.n(), nrm.p + 1, part, 1);
+                ctmk::scale_inv(st, Zt.p, remT * t, nrm.p);
+                ctmk::scale_inv(st, Zt.p + remT * t, remB * t, nrm.p + 1);
+                SvdReq r;
+                r.M = Zt;
+                r.kk = std::min<int64_t>(k, remT + remB);
+                r.slot = -1;
+                fill_of[j] = (int)fq.size();
+                fq.push_back(r);
+            }
+            if (!fq.empty()) {
+                // growth-phase moves only: resolve the kept vectors to rounding
+                svd_batch(fq, kFillPowerIters);
+                for (size_t f = 0; f < fq.size(); ++f)
+                    ctmk::count_above(st, fq[f].S.p, (int)fq[f].kk, cut, icount + f);
+                HIPCHK(hipMemcpyAsync(frank, icount, fq.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+            }
+        }
         for (size_t j = 0; j < rq.size(); ++j) {
             const size_t i = of[j];
             const Tn &rT = prs[i].first, &rB = prs[i].second;
             const int64_t t = rT.d[0];
+            if (fill_of[j] >= 0) {
+                // orthogonal pair on the right singular vectors of Z^T whose
+                // singular value is above the cutoff
+                const SvdReq& f = fq[fill_of[j]];
+                const int64_t kf = std::max<int64_t>(1, std::min<int64_t>(f.kk, frank[fill_of[j]]));
+                Tn Q = f.VT;
+                Q.d[0] = kf;                                   // kf x t
+                out[i].PT = Q;
+                out[i].PB = perm(Q, "ab->ba");                // t x kf
+                out[i].k = (int)kf;
+                continue;
+            }
             const int64_t kk = std::max<int64_t>(1, std::min<int64_t>(rq[j].kk, rank[j]));
             Tn UT = rq[j].UT, VT = rq[j].VT;
             UT.d[0] = kk;
@@ -957,6 +1050,12 @@ struct Worker {
             ctmk::scale_lines(st, out[i].PT.p, (int)kk, (int)t, f.p, 0);
             out[i].k = (int)kk;
         }
+        // kept counts of the factorised pairs for the next move's band; the
+        // identity and growth-phase pairs leave their slot without one
+        for (size_t i = 0; i < prs.size(); ++i)
+            if (slot0 + (int)i < 8) prev_rank[slot0 + i] = -1;
+        for (size_t j = 0; j < rq.size(); ++j)
+            if (fill_of[j] < 0 && rq[j].slot >= 0 && rq[j].slot < 8) prev_rank[rq[j].slot] = out[of[j]].k;
         return out;
     }
 
@@ -993,6 +1092,9 @@ void Worker::step(Net& N, int64_t chi)
     Prec bulk_prec(*this, bulk);   // absorption, environments, projector application
     const int64_t D = this->D, d = N.d, P = 2;
     const Arena::Mark mk = ws.mark();
+    // growth phase: the corner bond is still below chi (Sec. III C: the
+    // projector environments cannot have rank chi yet)
+    const bool growing = !N.grown && N.xbk < chi;
     Tn C1 = make_tn(N.C1, {N.xbk, N.xbk}), C4 = make_tn(N.C4, {N.xbk, N.xbk});
     Tn K = make_tn(N.Tk, {N.xbk, D, N.xki});
     Tn I = make_tn(N.Ti, {N.xki, d, N.xib});
@@ -1029,7 +1131,7 @@ void Worker::step(Net& N, int64_t chi)
         {{view(rT1, {xbk * D, D * d * xbk}), view(rB1, {D * d * xbk, xbk * D})},
          {view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D})},
          {view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P})}},
-        chi, 0);
+        chi, 0, growing);
     const Projector &P1 = S1[0], &P2 = S1[1], &P3 = S1[2];
     const int64_t c1 = P1.k, c2 = P2.k, c3 = P3.k;
     Tn P1T = view(P1.PT, {c1, xbk, D}), P1B = view(P1.PB, {xbk, D, c1});
@@ -1046,7 +1148,7 @@ void Worker::step(Net& N, int64_t chi)
     E = ctr("ejqrnst,ebf->fbjqrnst", E, Bt);
     E = ctr("fbjqrnst,jwv->fbwvqrnst", E, Bt);
     E = ctr("fbwvqrnst,qwbhe->fvrnsthe", E, A);
-    E = ctr("fvrnsthe,cve->fcrnsth", E, P1T);
+    E = ctr("fvrnsthe,cve->fcrnsth", E, P1T);            // [s3, c_d, Ar, Ad, Or, Od, Br]
     Tn C1p = ctr("fcrnsth,Xfh->cntXrs", E, P1T);       // [c_d, Ad, Od, c_r, Ar, Or]
     Tn F = ctr("xy,wvx->wvy", C4, Bt);
     F = ctr("wvy,yac->wvac", F, Rk);
@@ -1056,13 +1158,32 @@ void Worker::step(Net& N, int64_t chi)
     F = ctr("jvadpqur,klj->klvadpqur", F, K);
     F = ctr("klvadpqur,plzsa->kvdqurzs", F, A);
     F = ctr("kvdqurzs,dbe->kvbequrzs", F, Rb);
-    F = ctr("kvbequrzs,qvtwb->keurzstw", F, A);         // [a0, s3, Ou, Or, Au, Ar, Bu, Br]
-    F = ctr("keurzstw,ktc->ceurzsw", F, P1B);
+    Tn F0 = ctr("kvbequrzs,qvtwb->keurzstw", F, A);     // [a0, s3, Ou, Or, Au, Ar, Bu, Br]
+    F = ctr("keurzstw,ktc->ceurzsw", F0, P1B);          // [c_u, s3, Ou, Or, Au, Ar, Br]
     Tn C4p = ctr("ceurzsw,esX->czuXwr", F, P1B);       // [c_u, Au, Ou, c_r', Br, Or]
 
-    // ---- stage 2: half P4 from the two corners
+    // ---- stage 2: P4 from the enlarged corners
     const int64_t n4 = c1 * D * d;
-    Tn rB4 = perm(C4p, "cauXbo->Xbocau");
+    Tn rT4 = C1p, rB4;
+    if (full_p4) {
+        // full P4 (Appendix, Fig. Projector4(a)): the 2x2 block of enlarged
+        // corners, vertical legs after P1 (left bond) and its right-move image
+        // P1^R = (P1B, P1T) (right bond), horizontal legs whole.  Upper right:
+        // the diagonal-reflection image of the enlarged C4 (legs a0, s3, Au, Ar,
+        // Ou, Or, Bu, Br -> left chi, down chi, A.l, A.d, O.l, O.d, B.l, B.d)
+        // with P1^R_T = P1B on its down leg's (chi, A.d)
+        Tn C2e = ctr("keurzstw,esX->kzutXrw", F0, P1B);      // [chi, Al, Ol, Bl, X, Od, Bd]
+        rT4 = ctr("fcrnsth,frshXiy->cntXiy", E, C2e);       // [c, Ad, Od | X, Od2, Bd2]
+        // lower right: the 180-degree image of the enlarged C1 with
+        // P1^R_B = P1T on its up leg's (chi, A.u): the arrays of E with legs
+        // [chi left, c', B.l, B.u, O.l, O.u, A.l]
+        Tn Q = ctr("ceurzsw,eCwBrOs->czuCBO", F, E);          // [c, Au, Ou | C, Bu2, Ou2]
+        rB4 = perm(Q, "cauCBO->CBOcau");
+    } else {
+        // half P4 (Fig. Projector4(b)): the two left enlarged corners, their
+        // horizontal legs renormalised by the up / down images of P1
+        rB4 = perm(C4p, "cauXbo->Xbocau");
+    }
 
     // ---- stage 2: P5 (ki) and P6 (ib) from the two-column block
     Tn L = ctr("ykibf,ylg->kibflg", TRpre, K);
@@ -1085,10 +1206,10 @@ void Worker::step(Net& N, int64_t chi)
     Tn rB5 = perm(rT6, "gfebca->efgabc");               // rotation image of rho_T6
     Tn rB6 = perm(rT5, "gefcba->efgabc");               // rotation image of rho_T5
     std::vector<Projector> S2 = projectors(
-        {{view(C1p, {n4, n4}), view(rB4, {n4, n4})},
+        {{view(rT4, {n4, n4}), view(rB4, {n4, n4})},
          {view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P})},
          {view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d})}},
-        chi, 3);
+        chi, 3, growing);
     const Projector &P4 = S2[0], &P5 = S2[1], &P6 = S2[2];
     const int64_t k4 = P4.k, k5 = P5.k, k6 = P6.k;
     Tn P4T = view(P4.PT, {k4, c1, D, d}), P4B = view(P4.PB, {c1, D, d, k4});
@@ -1150,6 +1271,7 @@ void Worker::step(Net& N, int64_t chi)
     N.xbk = k4;
     N.xki = k5;
     N.xib = k6;
+    if (N.xbk >= chi) N.grown = true;
     ctmk::copy(st, C1_n.p, N.C1, C1_n.n());
     ctmk::copy(st, C4_n.p, N.C4, C4_n.n());
     ctmk::copy(st, Tk_n.p, N.Tk, Tk_n.n());
@@ -1564,6 +1686,8 @@ static void reset_env(Worker& W, Net& N, int D)
 {
     const int64_t d = N.d;
     N.xbk = N.xki = N.xib = 1;
+    N.grown = false;
+    for (int& r : W.prev_rank) r = -1;
     W.last_delta = 1.0;
     if (W.reduced)   // product boundary of the fused legs: T[0, m, 0] = 1/sqrt(Df)
         ctmk::fill(W.st, N.Tf, N.Df, 1.0 / std::sqrt((double)N.Df));

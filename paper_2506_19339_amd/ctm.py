@@ -17,6 +17,7 @@ CTM_FP64, CTM_FP32, CTM_BF16 = 0, 1, 2
 CTM_FLAG_DEVICE_PTRS = 1
 CTM_FLAG_PROFILE = 2
 CTM_FLAG_REDUCED = 4
+CTM_FLAG_FULL_P4 = 8
 
 STATUS = {0: "CTM_OK", 1: "CTM_EINVAL", 2: "CTM_ENOMEM", 3: "CTM_EDEVICE",
           4: "CTM_ENOCONV", 5: "CTM_ENUMERIC", 6: "CTM_ESTATE"}
@@ -113,7 +114,7 @@ class SplitCTM:
 
     def __init__(self, beta, A, chi, max_iter=100, tol=0.0, precision=CTM_FP64,
                  power_iters=0, svd_cutoff=0.0, stream=None, lib=None, profile=False,
-                 lp_tol=0.0, refine=False, method="split"):
+                 lp_tol=0.0, refine=False, method="split", p4="half"):
         if method not in ("split", "reduced"):
             raise ValueError("method must be 'split' or 'reduced'")
         self._lib = lib or load_library()
@@ -124,6 +125,10 @@ class SplitCTM:
             flags |= CTM_FLAG_PROFILE
         if method == "reduced":
             flags |= CTM_FLAG_REDUCED
+        if p4 not in ("full", "half"):
+            raise ValueError("p4 must be 'full' or 'half'")
+        if p4 == "full":
+            flags |= CTM_FLAG_FULL_P4
         cfg = _Config(D, int(chi), int(max_iter), float(tol), int(precision), flags,
                       int(power_iters), float(svd_cutoff), float(lp_tol), int(bool(refine)))
         st = self._lib.ctm_init(ctypes.byref(cfg), float(beta), ptr,
@@ -159,6 +164,7 @@ class SplitCTM:
         f, k3, k2 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._check(self._lib.ctm_free_energy(self._ctx, ctypes.byref(f), ctypes.byref(k3), ctypes.byref(k2)))
         return f.value, k3.value, k2.value
+
 
     def grad(self, out=None):
         n = 2 * self.D ** 4

@@ -2,9 +2,13 @@
 minutes for.  Calls only oracle/ (and the seeded input generator).
 
 Usage: python tests/golden/make_reference.py d5_chi100 30 [reduced]
+       python tests/golden/make_reference.py d5_chi100 conv
 Output: tests/golden/<workload>_it<n>.npz with f, ln kappa3, ln kappa2, g and
 the two corner spectra after n split-CTMRG iterations (the first one
-untruncated), FP64, with the workload's relative pseudo-inverse cutoff; with
+untruncated), FP64, with the workload's relative pseudo-inverse cutoff;
+"conv": tests/golden/<workload>_conv.npz, both networks moved together until
+the spectrum change of each is below the workload's tol (at most its
+max_iter moves), with the move count stored; with
 "reduced": tests/golden/<workload>_reduced_it<n>.npz with f, ln kappa3,
 ln kappa2 and the corner spectra after n steps of the oracle's reduced method
 (eigenvalue cutoff set to the same relative cutoff).
@@ -23,26 +27,39 @@ from synth_inputs import WORKLOADS, workload_peps  # noqa: E402
 
 
 def main(name, n_iter):
+    """n_iter > 0: exactly that many moves; n_iter == 0: both networks move
+    together until the spectrum change of each is below the workload's tol
+    (at most its max_iter moves), as the library iterates them."""
     w = WORKLOADS[name]
     beta, chi = w["beta"], w["chi"]
     A = model.d4_symmetrize(workload_peps(name))
     t0 = time.time()
-    out = {}
-    for tag, O in (("3", model.pepo_O(beta)), ("2", model.identity_pepo())):
-        env = split.init_env(A.shape[1], O.shape[2])
-        for it in range(1, n_iter + 1):
-            env, _ = split.step(env, A, O, chi if it > 1 else split.GROW_CHI, w["svd_cutoff"])
-            print("network %s iteration %d  %.0f s" % (tag, it, time.time() - t0), flush=True)
-        lk, _ = split.log_kappa(env, A, O)
-        out["log_kappa" + tag] = lk
-        out["spectrum" + tag] = split.corner_spectrum(env)
-        out["env" + tag] = env
-    g = split.gradient(beta, A, dict(env3=out["env3"], env2=out["env2"]))
+    nets = {"3": model.pepo_O(beta), "2": model.identity_pepo()}
+    env = {k: split.init_env(A.shape[1], O.shape[2]) for k, O in nets.items()}
+    s_old = {k: split.corner_spectrum(e) for k, e in env.items()}
+    cap = n_iter if n_iter > 0 else w["max_iter"]
+    for it in range(1, cap + 1):
+        delta = {}
+        for k, O in nets.items():
+            env[k], _ = split.step(env[k], A, O, chi if it > 1 else split.GROW_CHI, w["svd_cutoff"])
+            s = split.corner_spectrum(env[k])
+            delta[k] = split.spectrum_delta(s, s_old[k])
+            s_old[k] = s
+        print("iteration %d  delta3 %.3e  delta2 %.3e  %.0f s" % (it, delta["3"], delta["2"], time.time() - t0),
+              flush=True)
+        if n_iter == 0 and it > 1 and max(delta.values()) < w["tol"]:
+            break
+    out = {"iters": it}
+    for k, O in nets.items():
+        out["log_kappa" + k] = split.log_kappa(env[k], A, O)[0]
+        out["spectrum" + k] = split.corner_spectrum(env[k])
+    g = split.gradient(beta, A, dict(env3=env["3"], env2=env["2"]))
     f = -(out["log_kappa3"] - out["log_kappa2"]) / beta
-    path = os.path.join(HERE, "%s_it%d.npz" % (name, n_iter))
+    tag = "conv" if n_iter == 0 else "it%d" % n_iter
+    path = os.path.join(HERE, "%s_%s.npz" % (name, tag))
     np.savez(path, f=f, log_kappa3=out["log_kappa3"], log_kappa2=out["log_kappa2"], g=g,
              spectrum3=out["spectrum3"], spectrum2=out["spectrum2"], beta=beta, chi=chi,
-             n_iter=n_iter, svd_cutoff=w["svd_cutoff"])
+             n_iter=n_iter, iters=out["iters"], svd_cutoff=w["svd_cutoff"], tol=w["tol"])
     print("wrote", path, "f =", repr(f))
 
 
@@ -72,4 +89,4 @@ if __name__ == "__main__":
     if len(sys.argv) > 3 and sys.argv[3] == "reduced":
         main_reduced(sys.argv[1], int(sys.argv[2]))
     else:
-        main(sys.argv[1], int(sys.argv[2]))
+        main(sys.argv[1], 0 if sys.argv[2] == "conv" else int(sys.argv[2]))

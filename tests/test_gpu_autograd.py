@@ -73,14 +73,14 @@ def test_central_differences_d2():
 
 
 @pytest.mark.slow
+@pytest.mark.skip(reason="needs the implicit (fixed-point) adjoint, which is not built: the "
+                         "converged-environment gradient of Eq. (gradient expression) differs from "
+                         "d f_chi / dA by the finite-chi gap of the environment gradient, measured "
+                         "at 1.4e-4 and 4.5e-4 relative along two directions at this workload "
+                         "(independent of h from 1e-6 to 1e-4)")
 def test_central_differences_d5_chi100():
     """The differentiation workload (beta = 0.22, D = 5, chi = 100, FP32-rounded
-    parameters): the converged-environment gradient against central
-    differences of f at this chi.  The two differ by the finite-chi gap of the
-    environment gradient (it differentiates the 3x3 patch only, which is exact
-    at a stationary infinite environment); measured at 1.4e-4 and 4.5e-4
-    along two directions, independent of h (1e-6 and 1e-4 give the same), so
-    the bar here is 1e-3 and the 1e-5 bar is met only at small chi (test
-    above).  h = 1e-4 keeps the O(h^2) error at ~1e-8."""
+    parameters): the gradient against central differences of f at this chi,
+    h = 1e-6, relative 1e-5."""
     w = WORKLOADS["d5_chi100"]
-    _fd_check("d5_chi100", w["beta"], w["chi"], 1e-4, 2, 1e-3, max_iter=300, tol=1e-11)
+    _fd_check("d5_chi100", w["beta"], w["chi"], 1e-6, 2, 1e-5, max_iter=300, tol=1e-11)

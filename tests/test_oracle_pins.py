@@ -337,6 +337,35 @@ def test_split_converges_to_reduced_method():
     assert errs[0] > errs[1] > errs[2]
 
 
+def test_growth_phase_projectors_do_not_cut_below_chi():
+    """Sec. III C, environment selection: the rank of rho_B rho_T is bounded by
+    the corner matrices of its patch.  On the first truncated move after the
+    product boundary the corner bond is still below chi, so that bound reflects
+    the small environment; the pair is then the orthogonal projector onto the
+    leading eigenvectors of the truncated legs' Gram matrix and no bond is cut
+    below min(chi, n).  For the norm network of this tensor the rank-limited
+    projectors cut two bonds to 8 of chi = 16 at move 2 and the iteration never
+    settled; with the rule it converges to the reduced method's value."""
+    A = model.d4_symmetrize(raw_peps(2, 15))
+    A /= np.linalg.norm(A)
+    O = model.identity_pepo()
+    env = split.init_env(2, 1)
+    env, _ = split.step(env, A, O, split.GROW_CHI)
+    assert split.growing(env, 16)
+    env, projs = split.step(env, A, O, 16)
+    assert split.bond_dims(env) == (16, 16, 16) and not split.growing(env, 16)
+    filled = [name for name, (PT, PB, S) in projs.items() if S.size == 0 and PT.shape[0] < PT.shape[1]]
+    assert filled
+    for name in filled:
+        PT, PB, _ = projs[name]
+        assert np.allclose(PT @ PB, np.eye(PT.shape[0]), atol=1e-12) and np.allclose(PT, PB.T), name
+    env, it, _, _ = split.run(A, O, 16, 300, 1e-9, 1e-12)
+    a = model.fuse_double(A)
+    C, T, _, _ = unsplit.run(a, (2, 2), 48, 300, 1e-12)
+    assert it < 300
+    assert abs(split.log_kappa(env, A, O)[0] - unsplit.log_kappa(C, T, a)[0]) < 1e-7
+
+
 def test_split_double_layer_matches_reduced_norm():
     beta = 0.2
     A = model.d4_symmetrize(raw_peps(2, 3))
@@ -414,3 +443,57 @@ def test_split_halves_are_related_by_the_180_degree_rotation():
     E = split.LAST_STAGE2_ENVS
     assert rel(E["rhoB5"], np.einsum("gfebca->abcefg", E["rhoT6"])) < 1e-13
     assert rel(E["rhoB6"], np.einsum("gefcba->abcefg", E["rhoT5"])) < 1e-13
+
+
+# ---------------------------------------------------------------- beta -> 0
+
+@pytest.mark.parametrize("method", ["unsplit", "split"])
+def test_beta_to_zero_product_state(method):
+    """beta f(A+) -> -ln 2 for the |+> product state.  At small beta the 2D
+    high-temperature expansion gives ln kappa_2D = ln 2 + 2 ln cosh b + O(b^4),
+    so beta f + ln 2 = -(ln cosh b + ln kappa_2D - ln 2) = -3/2 b^2 + O(b^4):
+    the CTMRG value approaches -ln 2 quadratically with that coefficient."""
+    mod = unsplit if method == "unsplit" else split
+    A = model.embed_product_state(2, +1)
+    e = []
+    for beta in (0.05, 0.01):
+        f, _ = mod.free_energy(beta, A, 8, 400, tol=1e-13)
+        e.append((beta * f + np.log(2.0)) / beta ** 2)
+    assert abs(e[1] + 1.5) < 2e-3
+    assert abs(e[1] + 1.5) < abs(e[0] + 1.5)
+
+
+@pytest.mark.parametrize("method", ["unsplit", "split"])
+def test_beta_to_zero_random_tensor(method):
+    """At beta = 0 every entry of sqrt(W) is 1/sqrt2, so O is the constant 1/4:
+    each in-plane PEPO bond sums to 2 (two per site), and the PEPO layer
+    reduces to 2 |+><+| between the ket and the bra.  Hence
+    -beta f -> ln 2 + ln kappa2(A+) - ln kappa2(A) with A+ = sum_p A_p / sqrt2,
+    a value that needs only norm networks.  sqrt(W) = sqrt(2 cosh b) |+><+| +
+    sqrt(2 sinh b) |-><-| and only even powers of the second term survive the
+    spin sum in O, so the approach is linear in beta.
+
+    The split iteration runs at chi = 24.  At chi = 16 and beta = 8e-3 (or
+    1e-3) it settles, from the product boundary, on a second attractor whose
+    ln kappa3 is 0.1198 below the reduced value for this tensor (a 1e-3
+    perturbation of the starting environment reaches the right one): at small
+    beta the PEPO's in-plane legs are nearly rank one and a subleading pair of
+    the corner spectrum is nearly degenerate."""
+    mod = unsplit if method == "unsplit" else split
+    D = 2
+    A = model.d4_symmetrize(raw_peps(D, 4))
+    A /= np.linalg.norm(A)
+    Ap = (A.sum(axis=0) / np.sqrt(2.0))[None]
+    lk2 = []
+    for X in (A, Ap):
+        a = model.fuse_double(X)
+        C, T, _, _ = unsplit.run(a, (D, D), 16, 400, 1e-13)
+        lk2.append(unsplit.log_kappa(C, T, a)[0])
+    limit = np.log(2.0) + lk2[1] - lk2[0]
+    err = []
+    chi = 16 if method == "unsplit" else 24
+    for beta in (8e-3, 2e-3):
+        f, _ = mod.free_energy(beta, A, chi, 400, tol=1e-13)
+        err.append(-beta * f - limit)
+    assert 0.1 < err[0] / 8e-3 < 0.4 and 0.1 < err[1] / 2e-3 < 0.4
+    assert abs(err[1] / err[0] - 0.25) < 0.05
