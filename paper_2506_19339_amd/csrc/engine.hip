@@ -243,6 +243,7 @@ struct Worker {
     double* scal = nullptr;          // scratch scalars
     int* icount = nullptr;           // device ints for rank read-back
     int prev_rank[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // last kept count per projector slot (-1: none)
+    double prev_cut = 0.0;           // the cutoff those counts were taken with
     double* gws = nullptr;           // split-K partial products of the GEMMs
     int64_t gws_cap = 0;
     uint64_t svd_calls = 0;
@@ -980,6 +981,11 @@ struct Worker {
         HIPCHK(hipMemcpyAsync(cnt, icount, 2 * nq * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int rank[kMaxBatch] = {0};
+        // counts taken with another cutoff (a reduced-precision phase before
+        // the FP64 refinement) do not carry over
+        if (cut != prev_cut)
+            for (int& r : prev_rank) r = -1;
+        prev_cut = cut;
         for (size_t j = 0; j < nq; ++j) {
             const int prev = (rq[j].slot >= 0 && rq[j].slot < 8) ? prev_rank[rq[j].slot] : -1;
             rank[j] = prev < 0 ? cnt[j] : std::min(std::max(prev, cnt[nq + j]), cnt[j]);
