@@ -52,7 +52,8 @@ typedef struct ctm_ctx ctm_ctx;
 typedef enum {
     CTM_OK = 0,
     CTM_EINVAL = 1,     /* bad argument: beta <= 0, D < 1, chi < 1, NULL ... */
-    CTM_ENOMEM = 2,     /* device allocation failed                           */
+    CTM_ENOMEM = 2,     /* device memory: allocation failed, or the temporaries */
+                        /* exceed the fixed scratch of ctm_free_energy_noalloc */
     CTM_EDEVICE = 3,    /* a HIP call failed                                  */
     CTM_ENOCONV = 4,    /* max_iter reached before tol; results stay readable */
     CTM_ENUMERIC = 5,   /* NaN/Inf or a non-positive network value            */
@@ -157,6 +158,18 @@ ctm_status ctm_iterate_batch(ctm_ctx** cs, int n, int n_iter, int* iters_done, d
  * current environments (Eq. free energy expression).  Any output pointer may be
  * NULL.  CTM_ESTATE before the first iteration. */
 ctm_status ctm_free_energy(ctm_ctx* c, double* f, double* log_kappa3, double* log_kappa2);
+
+/* The same result as ctm_free_energy for callers that cannot allocate device
+ * memory (code that must not call hipMalloc, e.g. between graph captures or in
+ * tight serving loops): the contraction temporaries of both networks come from
+ * a fixed 128 MiB device array inside the library (64 MiB per network), one
+ * per GPU, held until the process ends; the call makes no hipMalloc or
+ * hipFree.  Returns CTM_ENOMEM (message in ctm_last_error) when the
+ * temporaries do not fit (e.g. D = 5, chi = 100); the context and its
+ * environments are then unchanged.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (two host threads, two contexts) race
+ * on it.  Same arguments, ownership and other errors as ctm_free_energy. */
+ctm_status ctm_free_energy_noalloc(ctm_ctx* c, double* f, double* log_kappa3, double* log_kappa2);
 
 /* g = -(2/beta) (E3/n1_3 - E2/n1_2), the environment of the bra tensor in the
  * 3x3 patch of each network normalised by that patch's value, projected onto

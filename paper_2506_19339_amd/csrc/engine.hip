@@ -38,6 +38,7 @@
 #include <stdexcept>
 #include <exception>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -71,6 +72,9 @@ class Arena {
     struct Chunk { char* p; size_t cap; };
     std::vector<Chunk> ch_;
     size_t cur_ = 0, off_ = 0;
+    bool fixed_ = false;
+    std::vector<Chunk> saved_;
+    size_t saved_cur_ = 0, saved_off_ = 0;
 
 public:
     struct Mark { size_t cur, off; };
@@ -78,6 +82,28 @@ public:
 
     Mark mark() const { return {cur_, off_}; }
     void release(Mark m) { cur_ = m.cur; off_ = m.off; }
+
+    // fixed-buffer mode (the allocation-free entry point): every allocation
+    // comes from [p, p + cap); running out raises CTM_ENOMEM instead of
+    // growing the arena with hipMalloc
+    void begin_fixed(char* p, size_t cap)
+    {
+        saved_.swap(ch_);
+        saved_cur_ = cur_;
+        saved_off_ = off_;
+        ch_.assign(1, Chunk{p, cap});
+        cur_ = off_ = 0;
+        fixed_ = true;
+    }
+    void end_fixed()
+    {
+        if (!fixed_) return;
+        saved_.swap(ch_);
+        saved_.clear();
+        cur_ = saved_cur_;
+        off_ = saved_off_;
+        fixed_ = false;
+    }
 
     double* alloc(int64_t count)
     {
@@ -92,6 +118,9 @@ public:
                 }
                 if (cur_ + 1 < ch_.size()) { ++cur_; off_ = 0; continue; }
             }
+            if (fixed_)
+                throw CtmError(CTM_ENOMEM, "the temporaries exceed the fixed scratch of the allocation-free "
+                                           "call (64 MiB per network)");
             size_t sz = std::max(bytes, (size_t)128 << 20);
             void* p = nullptr;
             hipError_t e = hipMalloc(&p, sz);
@@ -1855,6 +1884,43 @@ static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done,
     return first;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (ctm_free_energy_noalloc): the
+// contraction temporaries of both networks' values (one half each) come from
+// this file-scope device array instead of the context's workspace arena,
+// which grows by hipMalloc.  Each GPU the library runs on holds its own copy
+// until the process ends.  In host code the array's name is a host-side
+// stand-in: every host use goes through the per-device address returned by
+// hipGetSymbolAddress.  Every call on a GPU shares that GPU's array (calls
+// that overlap on one GPU race); nothing in it has to start at zero (every
+// temporary is written before it is read).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch[kMaxDevices] = {};
+
+// the address of `scratch` on device `device` (looked up once per device,
+// with that device current)
+static char* scratch_on(int device)
+{
+    REQUIRE(device >= 0 && device < kMaxDevices, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        HIPCHK(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess || p == nullptr)
+            throw CtmError(CTM_EDEVICE, "hipGetSymbolAddress of the scratch array failed");
+        g_scratch[device] = (char*)p;
+    }
+    return g_scratch[device];
+}
+
 extern "C" {
 
 int ctm_abi_version(void) { return CTM_ABI_VERSION; }
@@ -1978,6 +2044,45 @@ ctm_status ctm_free_energy(ctm_ctx* c, double* f, double* lk3, double* lk2)
         HIPCHK(hipMemcpyAsync(&h[3], c->net[1].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
         HIPCHK(hipStreamSynchronize(W.st));
         c->join();
+        if (h[2] != 0.0 || h[4] != 0.0 || !std::isfinite(h[0]))
+            throw CtmError(CTM_ENUMERIC, "non-positive or non-finite network value");
+    });
+    if (s == CTM_OK) {
+        if (f) *f = h[0];
+        if (lk3) *lk3 = h[1];
+        if (lk2) *lk2 = h[3];
+    }
+    return s;
+}
+
+ctm_status ctm_free_energy_noalloc(ctm_ctx* c, double* f, double* lk3, double* lk2)
+{
+    if (!c) return CTM_EINVAL;
+    if (c->iters == 0) { c->err = "no iteration done yet"; return CTM_ESTATE; }
+    double h[6] = {0, 0, 0, 0, 0, 0};
+    ctm_status s = guarded(c, [&] {
+        char* base = scratch_on(c->device);
+        const size_t half = kScratchBytes / 2;
+        c->w[0].ws.begin_fixed(base, half);
+        c->w[1].ws.begin_fixed(base + half, half);
+        try {
+            c->fork();
+            c->both([&](Worker& W, Net& N) { W.values(N, false); });
+            c->order(1, 0);
+            Worker& W = c->w[0];
+            ctmk::free_energy(W.st, c->net[0].sc + 4, c->net[1].sc + 4, c->beta, W.scal);
+            HIPCHK(hipMemcpyAsync(&h[0], W.scal, sizeof(double), hipMemcpyDeviceToHost, W.st));
+            HIPCHK(hipMemcpyAsync(&h[1], c->net[0].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
+            HIPCHK(hipMemcpyAsync(&h[3], c->net[1].sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, W.st));
+            HIPCHK(hipStreamSynchronize(W.st));
+            c->join();
+        } catch (...) {
+            // work already enqueued may still read the scratch: drain it
+            for (auto& x : c->w) (void)hipStreamSynchronize(x.st);
+            for (auto& x : c->w) x.ws.end_fixed();
+            throw;
+        }
+        for (auto& x : c->w) x.ws.end_fixed();
         if (h[2] != 0.0 || h[4] != 0.0 || !std::isfinite(h[0]))
             throw CtmError(CTM_ENUMERIC, "non-positive or non-finite network value");
     });

@@ -69,6 +69,7 @@ def load_library(path=None):
                                       ctypes.POINTER(ctypes.c_int), dp, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
     lib.ctm_free_energy.argtypes = [vp, dp, dp, dp]
+    lib.ctm_free_energy_noalloc.argtypes = [vp, dp, dp, dp]
     lib.ctm_grad.argtypes = [vp, vp]
     lib.ctm_magnetization.argtypes = [vp, dp]
     lib.ctm_bond_correlation.argtypes = [vp, dp]
@@ -85,7 +86,8 @@ def load_library(path=None):
     lib.ctm_status_string.argtypes = [ctypes.c_int]
     lib.ctm_status_string.restype = ctypes.c_char_p
     lib.ctm_abi_version.restype = ctypes.c_int
-    for fn in ("ctm_init", "ctm_iterate", "ctm_iterate_batch", "ctm_free_energy", "ctm_grad", "ctm_corner_spectrum",
+    for fn in ("ctm_init", "ctm_iterate", "ctm_iterate_batch", "ctm_free_energy", "ctm_free_energy_noalloc",
+               "ctm_grad", "ctm_corner_spectrum",
                "ctm_reset_tensor", "ctm_query"):
         getattr(lib, fn).restype = ctypes.c_int
     if path is None:
@@ -165,6 +167,12 @@ class SplitCTM:
         self._check(self._lib.ctm_free_energy(self._ctx, ctypes.byref(f), ctypes.byref(k3), ctypes.byref(k2)))
         return f.value, k3.value, k2.value
 
+    def free_energy_noalloc(self):
+        """free_energy() with the library's fixed scratch (ctm_free_energy_noalloc)."""
+        f, k3, k2 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.ctm_free_energy_noalloc(self._ctx, ctypes.byref(f), ctypes.byref(k3),
+                                                      ctypes.byref(k2)))
+        return f.value, k3.value, k2.value
 
     def grad(self, out=None):
         n = 2 * self.D ** 4
