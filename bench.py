@@ -26,6 +26,9 @@ import numpy as np  # noqa: E402
 
 from synth_inputs import WORKLOADS, raw_peps, workload_peps  # noqa: E402
 
+T_START = time.perf_counter()
+SERVING_MAX_ITER = 60
+
 PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
 
@@ -217,7 +220,7 @@ def main():
 
     roofline = None
     if not args.no_profile_pass:
-        print("profile pass", file=sys.stderr, flush=True)
+        print("profile pass" + " (%.0f s)" % (time.perf_counter() - T_START), file=sys.stderr, flush=True)
         c, pinfo = gpu_eval(ctm, torch, w, A, g, sp, profile=True)
         stats = {k: c.kernel_stats(k) for k in KERNEL_CLASSES}
         c.close()
@@ -241,7 +244,7 @@ def main():
     if not args.no_fp32_leg:
         # reduced-precision form: FP32 products / FP32 accumulation in the bulk
         # contractions, FP64 projectors, spectrum, f and g (same workload)
-        print("fp32 leg", file=sys.stderr, flush=True)
+        print("fp32 leg" + " (%.0f s)" % (time.perf_counter() - T_START), file=sys.stderr, flush=True)
         c, _ = gpu_eval(ctm, torch, w, A, g, sp, precision=ctm.CTM_FP32, refine=True)
         c.close()
         torch.cuda.synchronize()
@@ -262,7 +265,7 @@ def main():
     if not args.no_reduced_leg:
         # the reduced method (fused site tensors, C4v CTMRG) on the same
         # workload and the same kernels: the paper's comparison method
-        print("reduced-method leg", file=sys.stderr, flush=True)
+        print("reduced-method leg" + " (%.0f s)" % (time.perf_counter() - T_START), file=sys.stderr, flush=True)
         c, _ = gpu_eval(ctm, torch, w, A, g, sp, method="reduced")
         c.close()
         torch.cuda.synchronize()
@@ -293,7 +296,7 @@ def main():
         # the step after the hot path: L-BFGS on f from the workload tensor,
         # every evaluation warm-started from the last converged environments
         from paper_2506_19339_amd import optimize
-        print("lbfgs leg", file=sys.stderr, flush=True)
+        print("lbfgs leg" + " (%.0f s)" % (time.perf_counter() - T_START), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         with optimize.Optimizer(w["beta"], workload_peps(args.workload), w["chi"], env_tol=w["tol"],
@@ -310,26 +313,33 @@ def main():
         # beta ~ U[0.18, 0.26], D in {2,3,4,5}, chi in {16,32,64,100,128},
         # f + grad each) replayed in real time with continuous batching
         from paper_2506_19339_amd import serving
-        print("serving leg", file=sys.stderr, flush=True)
+        print("serving leg" + " (%.0f s)" % (time.perf_counter() - T_START), file=sys.stderr, flush=True)
         reqs = serving.trace_requests(args.serving_requests, 20.0, 1)
-        srv = serving.Server(hbm_budget=200 * serving.GiB, max_slots=16)
+        # each request gets at most SERVING_MAX_ITER moves (a server's work
+        # bound per request); one that has not met tol by then is returned
+        # flagged (CTM_ENOCONV) and counted in not_converged
+        srv = serving.Server(hbm_budget=200 * serving.GiB, max_slots=16, max_iter=SERVING_MAX_ITER)
         done = [0]
 
         def progress(req):
             done[0] += 1
             if done[0] % 16 == 0:
-                print("served %d / %d" % (done[0], len(reqs)), file=sys.stderr, flush=True)
+                print("served %d / %d (%.0f s)" % (done[0], len(reqs), time.perf_counter() - T_START),
+                      file=sys.stderr, flush=True)
 
         st = srv.run(reqs, realtime=True, on_done=progress)
         srv.close()
         serving = st.summary()
-        serving["trace"] = "%d requests, Poisson arrivals at 20/s (seed 1), tol 1e-9, max_iter 200" % len(reqs)
+        serving["trace"] = ("%d requests, Poisson arrivals at 20/s (seed 1), product state + 0.3 N(0,1) tensors, "
+                            "tol 1e-9, max_iter %d" % (len(reqs), SERVING_MAX_ITER))
         serving["failed"] = sum(1 for r in reqs if r.status not in (0, ctm.CTM_ENOCONV))
         serving["not_converged"] = sum(1 for r in reqs if r.status == ctm.CTM_ENOCONV)
+        serving["failures"] = ["request %d (D=%d, chi=%d, beta=%.4f): %s" % (r.rid, r.D, r.chi, r.beta, r.error)
+                               for r in reqs if r.status not in (0, ctm.CTM_ENOCONV)]
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("cpu baseline (oracle)", file=sys.stderr, flush=True)
+        print("cpu baseline (oracle)" + " (%.0f s)" % (time.perf_counter() - T_START), file=sys.stderr, flush=True)
         t3, t2 = cpu_baseline(args.workload, args.cpu_sample_iters)
         n_it = float(np.mean(iters))
         t_eval = n_it * (t3 + t2)

@@ -75,7 +75,6 @@ def ein(spec, *ops):
 from . import model
 
 SVD_CUTOFF = 1e-12
-RANK_BAND = 10.0     # hysteresis band of the kept rank (kept_rank)
 GROW_CHI = 1 << 30   # "no truncation" for the first move
 LAST_STAGE2_ENVS = {}  # rho_T / rho_B of P5 and P6 from the last stage2 call
 
@@ -105,27 +104,7 @@ def right_edge(env):
 # projector construction (Eqs. projector construction / ... 2)
 # ----------------------------------------------------------------------------
 
-def kept_rank(S, chi, cutoff, prev=None):
-    """Number of singular values kept: those above cutoff * S[0], at most chi.
-    With the bond's previous count prev (same projector slot, last move) the
-    count only moves when a value leaves the band cutoff ... cutoff * RANK_BAND:
-    prev is clamped between the counts above the band's upper and lower edges
-    (a value that fell below the cutoff comes back only above
-    cutoff * RANK_BAND).  Without the band a value sitting at the cutoff is
-    kept and dropped on alternate moves and the iteration ends in a two-move
-    cycle (the environment never settles).  Both edges are at or above the
-    cutoff, where the GPU's factorisation resolves the singular values."""
-    s0 = S[0]
-    if prev is None:
-        k = int(np.sum(S > cutoff * s0))
-    else:
-        hi = int(np.sum(S > cutoff * RANK_BAND * s0))
-        lo = int(np.sum(S > cutoff * s0))
-        k = min(max(prev, hi), lo)
-    return max(1, min(chi, k))
-
-
-def projector_pair(rhoB, rhoT, chi, cutoff=SVD_CUTOFF, fill=False, prev=None):
+def projector_pair(rhoB, rhoT, chi, cutoff=SVD_CUTOFF, fill=False):
     """rhoT: (trunc x remT) matrix, rhoB: (remB x trunc) matrix.
     Returns (PT [k x trunc], PB [trunc x k], kept singular values).
 
@@ -164,7 +143,7 @@ def projector_pair(rhoB, rhoT, chi, cutoff=SVD_CUTOFF, fill=False, prev=None):
         kf = max(1, min(k, int(np.sum(sz > cutoff * sz[0]))))
         Q = Uz[:, :kf]
         return Q.T.copy(), Q.copy(), np.zeros(0)
-    keep = kept_rank(S, chi, cutoff, prev)
+    keep = max(1, min(chi, keep))
     sinv = 1.0 / np.sqrt(S[:keep])
     PB = (rhoT @ Vh[:keep].T) * sinv[None, :]
     PT = sinv[:, None] * (U[:, :keep].T @ rhoB)
@@ -255,26 +234,21 @@ def B_of(A):
 # stage 1: P1, P2, P3
 # ----------------------------------------------------------------------------
 
-def _prev(env, slot):
-    r = env.get("ranks")
-    return None if r is None else r[slot]
-
-
 def stage1(env, A, O, chi, cutoff=SVD_CUTOFF, fill=False):
     up_ki, up_ib, up_bk = upper_sequence(env, A, O)
     lo_ki, lo_ib, lo_bk = lower_sequence(env, A, O)
     # P1: trunc (chi, B) ; rem (A, O, chiR)
     rT = _mat(up_bk.transpose(0, 1, 3, 2, 4), 2)                # (tbb,Bd) x (Ad,Od,rbb)
     rB = _mat(lo_bk.transpose(1, 2, 4, 0, 3), 3)                # (Au,Ou,rka) x (tka,Bu)
-    P1 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 0))
+    P1 = projector_pair(rB, rT, chi, cutoff, fill)
     # P2: trunc (chi, O, B) ; rem (A, p, chiR)
     rT = _mat(up_ki.transpose(0, 3, 4, 2, 1, 5), 3)             # (tkb,Ou,Bu) x (Ad,p,rkb)
     rB = _mat(lo_ki.transpose(4, 1, 5, 0, 2, 3), 3)             # (Ad,p,ria) x (tia,Ou,Bu)
-    P2 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 1))
+    P2 = projector_pair(rB, rT, chi, cutoff, fill)
     # P3: trunc (chi, B, q) ; rem (A, O, chiR)
     rT = _mat(up_ib.transpose(0, 4, 1, 3, 2, 5), 3)             # (tib,Bu,q) x (Ad,Od,rib)
     rB = _mat(lo_ib.transpose(3, 4, 5, 0, 2, 1), 3)             # (Ad,Od,rba) x (tba,Bu,q)
-    P3 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 2))
+    P3 = projector_pair(rB, rT, chi, cutoff, fill)
     return P1, P2, P3
 
 
@@ -373,11 +347,11 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF, fill=False, p4="half")
         # [chi left, c', B.l, B.u, O.l, O.u, A.l]
         rhoB4 = ein("csarhoy,sCyBoOr->cahCBO", K4, K1)                  # [c, Au, Ou | C, Bu2, Ou2]
         n4 = rhoT4.shape[0] * rhoT4.shape[1] * rhoT4.shape[2]
-        P4 = projector_pair(rhoB4.reshape(n4, -1).T, rhoT4.reshape(n4, -1), chi, cutoff, fill, _prev(env, 3))
+        P4 = projector_pair(rhoB4.reshape(n4, -1).T, rhoT4.reshape(n4, -1), chi, cutoff, fill)
     else:
         rT = C1p.reshape(nT, -1)                                # (c_d,Ad,Od) x (c_r,Ar,Or)
         rB = C4p.reshape(nT, -1).T                              # (c_r',Br,Or) x (c_u,Au,Ou)
-        P4 = projector_pair(rB, rT, chi, cutoff, fill, _prev(env, 3))
+        P4 = projector_pair(rB, rT, chi, cutoff, fill)
 
     # ---- P5 (ki bond, stage 2): two-column block cut at ki
     X = ein("xy,xus,sot,tbw->yuobw", C1, Tk, Ti, Tb)      # C1 + top cell 1
@@ -406,7 +380,7 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF, fill=False, p4="half")
     LR = ein("hpmsnuva,ehap->emsnuv", LR, P3T)            # [c2R,Ol2,Ou2,Bl2,Bu2,v3]
     rhoB5 = ein("epatyv,ftsyuv->eapsuf", LL, LR)          # [c2L,Ad1,p1,Ou2,Bu2,c2R]
     n5 = rhoT5.shape[0] * D * P
-    P5 = projector_pair(rhoB5.reshape(n5, -1).T, rhoT5.reshape(n5, -1), chi, cutoff, fill, _prev(env, 4))
+    P5 = projector_pair(rhoB5.reshape(n5, -1).T, rhoT5.reshape(n5, -1), chi, cutoff, fill)
 
     # ---- P6 (ib bond, stage 2): same block cut at ib
     X = ein("xy,xus,sot,tbw->yuobw", C1, Tk, Ti, Tb)
@@ -435,7 +409,7 @@ def stage2(env, A, O, chi, P1, P2, P3, cutoff=SVD_CUTOFF, fill=False, p4="half")
     LR6 = ein("kqnuvao,ekoa->eqnuv", LR6, P2T)            # [c3R,q2,Bl2,Bu2,v3]
     rhoB6 = ein("eyaov,fqyuv->eaouqf", LL6, LR6)          # [c3L,Ad1,Od1,Bu2,q2,c3R]
     n6 = rhoT6.shape[0] * D * d
-    P6 = projector_pair(rhoB6.reshape(n6, -1).T, rhoT6.reshape(n6, -1), chi, cutoff, fill, _prev(env, 5))
+    P6 = projector_pair(rhoB6.reshape(n6, -1).T, rhoT6.reshape(n6, -1), chi, cutoff, fill)
     LAST_STAGE2_ENVS.clear()
     LAST_STAGE2_ENVS.update(rhoT5=rhoT5, rhoB5=rhoB5, rhoT6=rhoT6, rhoB6=rhoB6)
     return P4, P5, P6, C1p, C4p
@@ -498,8 +472,6 @@ def step(env, A, O, chi, cutoff=SVD_CUTOFF, p4="half"):
     for k in new:
         new[k] = new[k] / np.linalg.norm(new[k])
     new["grown"] = bool(env.get("grown", False) or C1_n.shape[0] >= chi)
-    # kept counts of the factorised pairs (identity and growth-phase pairs: none)
-    new["ranks"] = [P[2].size if P[2].size else None for P in (P1, P2, P3, P4, P5, P6)]
     projs = dict(P1=P1, P2=P2, P3=P3, P4=P4, P5=P5, P6=P6)
     return new, projs
 

@@ -215,8 +215,10 @@ struct KStat {
 constexpr int kJacobiExact = 64;    // exact Jacobi SVD when min(m, n) <= this
 constexpr int64_t kJacobiExactArea = 18432;  // ... and m * n <= this (LDS-resident)
 constexpr int kOversample = 16;
-constexpr int kWarmPowerIters = 2;  // power steps when every subspace starts from last move's basis
-                                    // (the iteration continues across moves)
+constexpr int kWarmPowerIters = 4;  // power steps when every subspace starts from last move's basis
+                                    // (the iteration continues across moves).  At D = 5, chi = 100
+                                    // the converged f is 2.7e-10 from the oracle's with 2 steps,
+                                    // 7e-12 with 4 (6 % more time), 3e-13 with 8 (19 %)
 constexpr int kColdPowerIters = 10; // power steps from random normals
 // the same when the Rayleigh-Ritz core is less than 1.25 kk wide (kk > 112):
 // at D = 6, chi = 144 (core 160) ten cold steps resolve the early moves'
@@ -231,12 +233,8 @@ constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resi
 // spectrum in its Gram steps, so 1e-8 is the smallest relative singular value
 // it resolves in FP64.
 constexpr double kDefaultCutoff = 1e-8;
-// hysteresis band of a projector slot's kept count: it stays at last move's
-// value while that lies between the counts above cutoff * band and cutoff (a
-// value sitting at the cutoff otherwise enters and leaves on alternate moves
-// and the environment cycles)
-constexpr double kRankBand = 10.0;
 constexpr int kJacobiSweeps = 40;
+constexpr int64_t kCholRegRows = 128;  // rows of the register-resident Cholesky-QR kernel
 constexpr int kFillPowerIters = 40; // power steps of the growth-phase Gram factorisations
 constexpr int kMaxBatch = 16;       // projectors factorised together
 constexpr int kMaxIterateBatch = 64; // contexts advanced by one ctm_iterate_batch call
@@ -271,8 +269,6 @@ struct Worker {
     double* part = nullptr;          // reduction partials
     double* scal = nullptr;          // scratch scalars
     int* icount = nullptr;           // device ints for rank read-back
-    int prev_rank[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // last kept count per projector slot (-1: none)
-    double prev_cut = 0.0;           // the cutoff those counts were taken with
     double* gws = nullptr;           // split-K partial products of the GEMMs
     int64_t gws_cap = 0;
     uint64_t svd_calls = 0;
@@ -280,6 +276,7 @@ struct Worker {
     int64_t trace_perm = 0;          // testing aid: log permutes of at least this many elements
     bool trace_gemm = false;         // testing aid: log GEMM shapes
     bool no_group = false;           // testing aid: one launch per product in mm_group
+    bool trace_ranks = false;        // testing aid: log the kept rank of every projector
     bool trace_sweeps = false;       // testing aid: log the sweeps of every Jacobi job (profile mode)
     bool warm_starts = true;         // keep each slot's Ritz basis for the next move
     bool reduced = false;            // reduced (unsplit) C4v CTMRG on the fused site tensor
@@ -315,7 +312,7 @@ struct Worker {
         HIPCHK(hipEventCreateWithFlags(&ev_side_done, hipEventDisableTiming));
         part = keep(ctmk::kRedBlocks);
         scal = keep(16);
-        icount = (int*)keep(2 * kMaxBatch);
+        icount = (int*)keep(kMaxBatch);
         gws_cap = (int64_t)1 << 22;   // 32 MiB
         gws = keep(gws_cap);
         if (profiling) sweeps_dev = (int*)keep(kSweepSlots / 2);
@@ -436,7 +433,7 @@ struct Worker {
     }
     void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
               int64_t sA, const double* B, int64_t ldb, int64_t sB, double* C, int64_t ldc,
-              int64_t sC, int64_t nb)
+              int64_t sC, int64_t nb, double alpha = 1.0, double beta = 0.0)
     {
         if (trace_gemm)
             std::fprintf(stderr, "gemm %lld %lld %lld %lld %d %d %d\n", (long long)M, (long long)N, (long long)K,
@@ -444,15 +441,15 @@ struct Worker {
         hipEvent_t e = prof_begin();
         hipEvent_t mid = profiling ? ev_get() : nullptr;
         if (cur == CTM_FP64)
-            ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, (int)nb,
-                           gws, gws_cap, mid);
+            ctmk::gemm_f64(st, ta, tb, (int)M, (int)N, (int)K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
+                           (int)nb, gws, gws_cap, mid);
         else
-            ctmk::gemm_lp(st, cur, ta, tb, (int)M, (int)N, (int)K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC,
+            ctmk::gemm_lp(st, cur, ta, tb, (int)M, (int)N, (int)K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
                           (int)nb, gws, gws_cap, mid);
         if (profiling)
             prof_gemm(e, mid, 2.0 * (double)M * (double)N * (double)K * (double)nb,
                       8.0 * ((double)M * K + (double)K * N + (double)M * N) * (double)nb,
-                      ctmk::gemm_split_plan((int)M, (int)N, (int)K, (int)nb, gws_cap) > 1);
+                      beta == 0.0 && ctmk::gemm_split_plan((int)M, (int)N, (int)K, (int)nb, gws_cap) > 1);
     }
     // profile mode: product kernel [e, mid], split-K reduction [mid, end]
     void prof_gemm(hipEvent_t e, hipEvent_t mid, double flops, double bytes, bool split)
@@ -577,6 +574,32 @@ struct Worker {
         return t;
     }
 
+    // Keeps the listed tensors and returns everything else allocated since m
+    // to the arena, so that a chain of contractions holds its intermediates
+    // only while it runs.  Each kept tensor is copied above the arena's top
+    // first and then down from m: a bump allocator places a subset of its
+    // earlier allocations no higher than they were, so neither copy overlaps
+    // its source.  Not used while work is on the side stream.
+    void settle(Arena::Mark m, std::initializer_list<Tn*> keep)
+    {
+        REQUIRE(!on_side, "settle during side work");
+        double* up[8];
+        int n = 0;
+        REQUIRE(keep.size() <= 8, "settle: too many tensors");
+        for (Tn* t : keep) {
+            up[n] = ws.alloc(t->n());
+            ctmk::copy(st, t->p, up[n], t->n());
+            ++n;
+        }
+        ws.release(m);
+        n = 0;
+        for (Tn* t : keep) {
+            double* q = ws.alloc(t->n());
+            ctmk::copy(st, up[n++], q, t->n());
+            t->p = q;
+        }
+    }
+
     // ctr("ab,bc->ac", A, B): labelled pairwise contraction.  Labels shared by
     // A, B and the output are batch labels; shared by A and B only are summed.
     Tn ctr(const char* spec, const Tn& A0, const Tn& B0)
@@ -630,9 +653,6 @@ struct Worker {
         }
         if (lb == bt + cord + fbB) { okB = true; tB = false; }
         else if (lb == bt + fbB + cord) { okB = true; tB = true; }
-        Tn Ao = A, Bo = B;
-        if (!okA) { Ao = permute_labels(A, la, bt + faA + cord); tA = false; }
-        if (!okB) { Bo = permute_labels(B, lb, bt + cord + fbB); tB = false; }
         int64_t M = 1, N = 1, K = 1, nb = 1;
         for (char c : faA) M *= dim[(int)c];
         for (char c : fbB) N *= dim[(int)c];
@@ -643,7 +663,14 @@ struct Worker {
         int64_t od[kMaxRank];
         int orank = 0;
         for (char c : nat) od[orank++] = dim[(int)c];
+        // the result first, then the transposed operands above it, which are
+        // returned to the arena once the product is enqueued (later work on
+        // this stream reuses them in stream order; side work keeps them)
         Tn C = tmp_dims(od, orank);
+        const Arena::Mark opm = ws.mark();
+        Tn Ao = A, Bo = B;
+        if (!okA) { Ao = permute_labels(A, la, bt + faA + cord); tA = false; }
+        if (!okB) { Bo = permute_labels(B, lb, bt + cord + fbB); tB = false; }
         if (M == 1 && N == 1 && nb == 1) {
             ctmk::dot(st, Ao.p, Bo.p, K, C.p, part, 0);
         } else {
@@ -651,6 +678,7 @@ struct Worker {
             gemm(tA, tB, M, N, K, Ao.p, tA ? M : K, M * K, Bo.p, tB ? K : N, K * N,
                  C.p, N, M * N, nb);
         }
+        if (!on_side) ws.release(opm);
         if (lo == nat) return C;
         // keep the natural order; record where each logical axis is stored
         Tn L = C;
@@ -760,6 +788,11 @@ struct Worker {
     // Y <- T Y.  The factors of all problems are built in one launch.
     void cholqr_pass(std::vector<Tn>& Ys)
     {
+        for (const Tn& y : Ys)
+            if (y.d[0] > kCholRegRows) {
+                cholqr_pass_blocked(Ys);
+                return;
+            }
         std::vector<Tn> Ts(Ys.size());
         for (size_t b0 = 0; b0 < Ys.size(); b0 += ctmk::kMaxJacobiBatch) {
             const size_t b1 = std::min(Ys.size(), b0 + (size_t)ctmk::kMaxJacobiBatch);
@@ -779,6 +812,46 @@ struct Worker {
             prof_end(2, e, fl);
         }
         Ys = mm_group(Ts, false, Ys, false);
+    }
+
+    // Y with more than kCholRegRows rows: the head H (first kCholRegRows
+    // rows) by one Cholesky-QR pass (-> Q1), the tail R projected off it,
+    // R <- R - (R Q1^T) Q1, and then given a pass of its own (recursively):
+    // block classical Gram-Schmidt whose factorisations all fit the
+    // register-resident kernel.  Two passes (orth) re-project the tail, which
+    // restores the orthogonality between the blocks.
+    void cholqr_pass_blocked(std::vector<Tn>& Ys)
+    {
+        const size_t nb = Ys.size();
+        std::vector<Tn> H(nb), R;
+        std::vector<size_t> r_of;
+        for (size_t i = 0; i < nb; ++i) {
+            const Tn Y = mat(Ys[i]);
+            const int64_t k = Y.d[0], n = Y.d[1], k1 = std::min<int64_t>(k, kCholRegRows);
+            H[i] = make_tn(Y.p, {k1, n});
+            if (k > k1) {
+                R.push_back(make_tn(Y.p + k1 * n, {k - k1, n}));
+                r_of.push_back(i);
+            }
+        }
+        cholqr_pass(H);
+        std::vector<Tn> Hr(R.size());
+        for (size_t j = 0; j < R.size(); ++j) Hr[j] = H[r_of[j]];
+        const std::vector<Tn> C = mm_group(R, false, Hr, true);        // R Q1^T
+        for (size_t j = 0; j < R.size(); ++j) {
+            const int64_t k2 = R[j].d[0], n = R[j].d[1], k1 = Hr[j].d[0];
+            gemm(false, false, k2, n, k1, C[j].p, k1, 0, Hr[j].p, n, 0, R[j].p, n, 0, 1, -1.0, 1.0);
+        }
+        cholqr_pass(R);
+        for (size_t i = 0; i < nb; ++i) Ys[i] = H[i];
+        for (size_t j = 0; j < R.size(); ++j) {
+            const size_t i = r_of[j];
+            const int64_t k1 = H[i].d[0], k2 = R[j].d[0], n = H[i].d[1];
+            Tn Q = tmp({k1 + k2, n});
+            ctmk::copy(st, H[i].p, Q.p, k1 * n);
+            ctmk::copy(st, R[j].p, Q.p + k1 * n, k2 * n);
+            Ys[i] = Q;
+        }
     }
 
     // rows of every Y -> orthonormal rows spanning the same space (shifted
@@ -998,26 +1071,19 @@ struct Worker {
         // order the unit roundoff; singular values below that level are noise
         if (bulk == CTM_FP32) cut = std::max(cut, lp_cut > 0 ? lp_cut : kLpCutFp32);
         if (bulk == CTM_BF16) cut = std::max(cut, lp_cut > 0 ? lp_cut : kLpCutBf16);
-        // counts above cut (plain rule) and above cut * band: a slot's kept
-        // count stays at last move's value while that lies between the two
-        // (the hysteresis of the oracle's split.kept_rank)
-        const size_t nq = rq.size();
-        for (size_t j = 0; j < nq; ++j) {
-            ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut, icount + j);
-            ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut * kRankBand, icount + nq + j);
-        }
-        int cnt[2 * kMaxBatch] = {0};
-        HIPCHK(hipMemcpyAsync(cnt, icount, 2 * nq * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        for (size_t j = 0; j < rq.size(); ++j) ctmk::count_above(st, rq[j].S.p, (int)rq[j].kk, cut, icount + j);
         int rank[kMaxBatch] = {0};
-        // counts taken with another cutoff (a reduced-precision phase before
-        // the FP64 refinement) do not carry over
-        if (cut != prev_cut)
-            for (int& r : prev_rank) r = -1;
-        prev_cut = cut;
-        for (size_t j = 0; j < nq; ++j) {
-            const int prev = (rq[j].slot >= 0 && rq[j].slot < 8) ? prev_rank[rq[j].slot] : -1;
-            rank[j] = prev < 0 ? cnt[j] : std::min(std::max(prev, cnt[nq + j]), cnt[j]);
+        HIPCHK(hipMemcpyAsync(rank, icount, rq.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (trace_ranks) {
+            for (size_t j = 0; j < rq.size(); ++j) {
+                std::vector<double> sv((size_t)rq[j].kk);
+                HIPCHK(hipMemcpy(sv.data(), rq[j].S.p, sv.size() * sizeof(double), hipMemcpyDeviceToHost));
+                const int r = rank[j];
+                std::fprintf(stderr, "rank P%d %d/%lld last %.3e next %.3e\n", slot0 + (int)j + 1, r,
+                             (long long)rq[j].kk, r > 0 ? sv[r - 1] / sv[0] : 0.0,
+                             r < (int)sv.size() ? sv[r] / sv[0] : 0.0);
+            }
         }
         // P_B = rho_T V S^-1/2 and P_T = S^-1/2 U^T rho_B amplify the directions
         // of small singular values: FP64 in every form
@@ -1085,12 +1151,6 @@ struct Worker {
             ctmk::scale_lines(st, out[i].PT.p, (int)kk, (int)t, f.p, 0);
             out[i].k = (int)kk;
         }
-        // kept counts of the factorised pairs for the next move's band; the
-        // identity and growth-phase pairs leave their slot without one
-        for (size_t i = 0; i < prs.size(); ++i)
-            if (slot0 + (int)i < 8) prev_rank[slot0 + i] = -1;
-        for (size_t j = 0; j < rq.size(); ++j)
-            if (fill_of[j] < 0 && rq[j].slot >= 0 && rq[j].slot < 8) prev_rank[rq[j].slot] = out[of[j]].k;
         return out;
     }
 
@@ -1138,6 +1198,10 @@ void Worker::step(Net& N, int64_t chi)
     Tn O = make_tn(N.O, {P, P, d, d, d, d});
     // right / bottom edge chain (D2 relations)
     Tn Rk = perm(Bt, "bma->amb"), Ri = perm(I, "bma->amb"), Rb = perm(K, "bma->amb");
+    // Each section below ends by settling its results (settle), so that the
+    // step holds the intermediates of one chain at a time: the largest is
+    // chi^2 D^3 d^2 P doubles (Sec. III C, memory cost of the split scheme).
+    const Arena::Mark m_s1 = ws.mark();
 
     // ---- top row C1 T1(k,i,b) C2 and the upper halves at ki, ib, bk
     Tn H = ctr("xy,xkc->ykc", C1, K);
@@ -1167,13 +1231,18 @@ void Worker::step(Net& N, int64_t chi)
          {view(rT2, {xki * d * D, D * P * xib}), view(rB2, {D * P * xib, xki * d * D})},
          {view(rT3, {xib * D * P, D * d * xki}), view(rB3, {D * d * xki, xib * D * P})}},
         chi, 0, growing);
+    settle(m_s1, {&TRpre, &S1[0].PT, &S1[0].PB, &S1[1].PT, &S1[1].PB, &S1[2].PT, &S1[2].PB});
     const Projector &P1 = S1[0], &P2 = S1[1], &P3 = S1[2];
     const int64_t c1 = P1.k, c2 = P2.k, c3 = P3.k;
     Tn P1T = view(P1.PT, {c1, xbk, D}), P1B = view(P1.PB, {xbk, D, c1});
     Tn P2T = view(P2.PT, {c2, xki, d, D}), P2B = view(P2.PB, {xki, d, D, c2});
     Tn P3T = view(P3.PT, {c3, xib, D, P}), P3B = view(P3.PB, {xib, D, P, c3});
 
-    // ---- enlarged corners with the stage-1 bra projections on both legs
+    // ---- enlarged corners with the stage-1 bra projections on both legs.
+    // The bra site and the projector that cuts its leg are joined into a
+    // small piece before they meet the ket and PEPO layers, so that no
+    // intermediate carries D^4 (chi^2 D^3 d^2 P at most).
+    const Arena::Mark m_e = ws.mark();
     Tn Etop = ctr("xy,xkc->ykc", C1, K);
     Tn E = ctr("ykc,ylg->kclg", Etop, K);
     E = ctr("kclg,plkrn->cgprn", E, A);
@@ -1181,20 +1250,33 @@ void Worker::step(Net& N, int64_t chi)
     E = ctr("egiprn,gmj->eijmprn", E, I);
     E = ctr("eijmprn,pqmist->ejqrnst", E, O);
     E = ctr("ejqrnst,ebf->fbjqrnst", E, Bt);
-    E = ctr("fbjqrnst,jwv->fbwvqrnst", E, Bt);
-    E = ctr("fbwvqrnst,qwbhe->fvrnsthe", E, A);
-    E = ctr("fvrnsthe,cve->fcrnsth", E, P1T);            // [s3, c_d, Ar, Ad, Or, Od, Br]
+    Tn G = ctr("jwv,cve->jwce", Bt, P1T);                 // bra edge cut by P1
+    G = ctr("jwce,qwbhe->jcqbh", G, A);                   // [tib, c_d, q, Bu, Br]
+    E = ctr("fbjqrnst,jcqbh->fcrnsth", E, G);            // [s3, c_d, Ar, Ad, Or, Od, Br]
     Tn C1p = ctr("fcrnsth,Xfh->cntXrs", E, P1T);       // [c_d, Ad, Od, c_r, Ar, Or]
+    if (full_p4) settle(m_e, {&C1p, &E});
+    else settle(m_e, {&C1p});
+    const Arena::Mark m_f = ws.mark();
     Tn F = ctr("xy,wvx->wvy", C4, Bt);
     F = ctr("wvy,yac->wvac", F, Rk);
     F = ctr("wvac,jmw->jmvac", F, I);
     F = ctr("jmvac,cod->jmvaod", F, Ri);
     F = ctr("jmvaod,pqmuro->jvadpqur", F, O);
-    F = ctr("jvadpqur,klj->klvadpqur", F, K);
-    F = ctr("klvadpqur,plzsa->kvdqurzs", F, A);
-    F = ctr("kvdqurzs,dbe->kvbequrzs", F, Rb);
-    Tn F0 = ctr("kvbequrzs,qvtwb->keurzstw", F, A);     // [a0, s3, Ou, Or, Au, Ar, Bu, Br]
-    F = ctr("keurzstw,ktc->ceurzsw", F0, P1B);          // [c_u, s3, Ou, Or, Au, Ar, Br]
+    Tn F0;
+    if (full_p4) {
+        // the full P4 also needs the enlarged corner before P1 (F0)
+        F = ctr("jvadpqur,klj->klvadpqur", F, K);
+        F = ctr("klvadpqur,plzsa->kvdqurzs", F, A);
+        F = ctr("kvdqurzs,dbe->kvbequrzs", F, Rb);
+        F0 = ctr("kvbequrzs,qvtwb->keurzstw", F, A);     // [a0, s3, Ou, Or, Au, Ar, Bu, Br]
+        F = ctr("keurzstw,ktc->ceurzsw", F0, P1B);        // [c_u, s3, Ou, Or, Au, Ar, Br]
+    } else {
+        Tn Z = ctr("dbe,qvtwb->deqvtw", Rb, A);            // bra site on the bottom edge
+        F = ctr("jvadpqur,deqvtw->japuretw", F, Z);
+        Tn Y = ctr("klj,ktc->ljtc", K, P1B);               // left edge cut by P1
+        F = ctr("japuretw,ljtc->apurewlc", F, Y);
+        F = ctr("apurewlc,plzsa->ceurzsw", F, A);         // [c_u, s3, Ou, Or, Au, Ar, Br]
+    }
     Tn C4p = ctr("ceurzsw,esX->czuXwr", F, P1B);       // [c_u, Au, Ou, c_r', Br, Or]
 
     // ---- stage 2: P4 from the enlarged corners
@@ -1219,8 +1301,11 @@ void Worker::step(Net& N, int64_t chi)
         // horizontal legs renormalised by the up / down images of P1
         rB4 = perm(C4p, "cauXbo->Xbocau");
     }
+    if (full_p4) settle(m_f, {&C4p, &rT4, &rB4});
+    else settle(m_f, {&C4p, &rB4});
 
     // ---- stage 2: P5 (ki) and P6 (ib) from the two-column block
+    const Arena::Mark m_s3 = ws.mark();
     Tn L = ctr("ykibf,ylg->kibflg", TRpre, K);
     Tn ULraw = ctr("kibflg,plkrn->ibfgpnr", L, A);      // [Ou, Bu, s3, tkb, p, Ad, Ar]
     Tn UL5 = ctr("ibfgpnr,cgib->cfpnr", ULraw, P2T);   // [c2L, s3, p, Ad, Ar]
@@ -1231,12 +1316,16 @@ void Worker::step(Net& N, int64_t chi)
     Tn URraw = ctr("fkibrg,plkrn->fibgpln", J, A);      // [s3, Ou, Bu, rkb, p, Al, Ad]
     Tn UR5 = ctr("fibgpln,gnpc->fiblc", URraw, P3B);   // P2^R_T = P3_B: [s3, Ou2, Bu2, Al2, c2R]
     Tn rT5 = ctr("cfpnr,fibrd->cnpibd", UL5, UR5);      // [c2L, Ad1, p1, Ou2, Bu2, c2R]
+    const Arena::Mark m_h = ws.mark();
     Tn H6 = ctr("ibfgpnr,gmj->ibfjmpnr", ULraw, I);
     H6 = ctr("ibfjmpnr,pqmist->bfjqnrst", H6, O);
     Tn UL6 = ctr("bfjqnrst,cjbq->cfnrst", H6, P3T);    // [c3L, s3, Ad1, Ar1, Or1, Od1]
+    settle(m_h, {&UL6});
+    const Arena::Mark m_k = ws.mark();
     Tn K6 = ctr("fibgpln,gsh->fibpslnh", URraw, Ri);
     K6 = ctr("fibpslnh,pqmist->fblnhqmt", K6, O);
     Tn UR6 = ctr("fblnhqmt,htnc->fblqmc", K6, P2B);    // P3^R_T = P2_B: [s3, Bu2, Al2, q2, Ol2, c3R]
+    settle(m_k, {&UR6});
     Tn rT6 = ctr("cfnrst,fbrqsd->cntbqd", UL6, UR6);    // [c3L, Ad1, Od1, Bu2, q2, c3R]
     Tn rB5 = perm(rT6, "gfebca->efgabc");               // rotation image of rho_T6
     Tn rB6 = perm(rT5, "gefcba->efgabc");               // rotation image of rho_T5
@@ -1245,6 +1334,7 @@ void Worker::step(Net& N, int64_t chi)
          {view(rT5, {c2 * D * P, d * D * c3}), view(rB5, {d * D * c3, c2 * D * P})},
          {view(rT6, {c3 * D * d, D * P * c2}), view(rB6, {D * P * c2, c3 * D * d})}},
         chi, 3, growing);
+    settle(m_s3, {&S2[0].PT, &S2[0].PB, &S2[1].PT, &S2[1].PB, &S2[2].PT, &S2[2].PB});
     const Projector &P4 = S2[0], &P5 = S2[1], &P6 = S2[2];
     const int64_t k4 = P4.k, k5 = P5.k, k6 = P6.k;
     Tn P4T = view(P4.PT, {k4, c1, D, d}), P4B = view(P4.PB, {c1, D, d, k4});
@@ -1366,9 +1456,11 @@ void Worker::values(Net& N, bool with_env)
     ctmk::copy(st, s0.p, N.sc + 3, 1);
     ctmk::log_kappa(st, N.sc, N.sc + 4);
     if (with_env) {
+        // the bottom edge joins the lower half first, so that no intermediate
+        // carries D^4
         Tn G = ctr("jqtnbk,jwv->qtnbwvk", upib, Bt);
-        G = ctr("qtnbwvk,ksz->qtnbwvsz", G, Rb);
-        Tn Env = mat(ctr("qtnbwvsz,vntez->qwbse", G, BR));   // [q, Bl, Bu, Br, Bd]
+        Tn RB = ctr("ksz,vntez->ksvnte", Rb, BR);
+        Tn Env = mat(ctr("qtnbwvk,ksvnte->qwbse", G, RB));   // [q, Bl, Bu, Br, Bd]
         ctmk::copy(st, Env.p, N.E, Env.n());
         ctmk::dot(st, Env.p, this->A, Env.n(), N.sc + 6, part, 0);
     }
@@ -1722,7 +1814,6 @@ static void reset_env(Worker& W, Net& N, int D)
     const int64_t d = N.d;
     N.xbk = N.xki = N.xib = 1;
     N.grown = false;
-    for (int& r : W.prev_rank) r = -1;
     W.last_delta = 1.0;
     if (W.reduced)   // product boundary of the fused legs: T[0, m, 0] = 1/sqrt(Df)
         ctmk::fill(W.st, N.Tf, N.Df, 1.0 / std::sqrt((double)N.Df));
@@ -1982,6 +2073,7 @@ ctm_status ctm_init(const ctm_config* cfg, double beta, const double* A, void* h
             if (const char* e = std::getenv("CTM_TRACE_PERMUTE")) x.trace_perm = std::atoll(e);   // testing aid
             if (const char* e = std::getenv("CTM_LP_CUTOFF")) x.lp_cut = std::atof(e);            // testing aid
             if (std::getenv("CTM_TRACE_GEMM")) x.trace_gemm = true;                                // testing aid
+            if (std::getenv("CTM_TRACE_RANKS")) x.trace_ranks = true;                              // testing aid
             if (std::getenv("CTM_NO_WARM_SVD")) x.warm_starts = false;                             // testing aid
             if (std::getenv("CTM_NO_GEMM_GROUP")) x.no_group = true;                               // testing aid
             if (std::getenv("CTM_TRACE_SWEEPS")) x.trace_sweeps = true;                            // testing aid

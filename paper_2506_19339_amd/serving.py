@@ -43,6 +43,7 @@ class Request:
     g: np.ndarray = None
     iters: int = 0
     status: int = -1
+    error: str = ""          # the library's message when status is an error
     warm: bool = False
     t_admit: float = float("nan")
     t_done: float = float("nan")
@@ -179,6 +180,8 @@ class Server:
                     keep.append((req, c, A))
                     continue
                 req.status = st
+                if st not in (0, ctm.CTM_ENOCONV):
+                    req.error = c._lib.ctm_last_error(c._ctx).decode()
                 if st in (0, ctm.CTM_ENOCONV):
                     try:
                         req.f = c.free_energy()[0]
@@ -191,6 +194,7 @@ class Server:
                             req.g = c.grad()
                     except ctm.CtmError as e:   # e.g. a negative network value
                         req.status = e.status
+                        req.error = str(e)
                         st = e.status
                 req.t_done = now()
                 stats.latencies.append(req.latency)
@@ -221,13 +225,14 @@ class Server:
 
 def trace_requests(n_requests=256, mean_rate=20.0, seed=1, D_set=None, chi_set=None):
     """The serving workload: Poisson arrivals, beta ~ U[0.18, 0.26], D and chi
-    drawn per request, A seeded N(0, 1) (seed 1000 + i)."""
-    from synth_inputs import raw_peps, serving_trace
+    drawn per request, A the product state plus 0.3 N(0, 1) noise (seed
+    1000 + i)."""
+    from synth_inputs import serving_peps, serving_trace
     reqs = []
     for i, r in enumerate(serving_trace(n_requests, mean_rate, seed)):
         D = r["D"] if D_set is None else D_set[i % len(D_set)]
         chi = r["chi"] if chi_set is None else chi_set[i % len(chi_set)]
-        reqs.append(Request(rid=i, beta=r["beta"], A=raw_peps(D, r["seed"]), chi=chi,
+        reqs.append(Request(rid=i, beta=r["beta"], A=serving_peps(D, r["seed"]), chi=chi,
                             t_arrival=r["t_arrival"]))
     return reqs
 

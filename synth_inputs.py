@@ -42,6 +42,17 @@ def raw_peps(D, seed, fp32_params=False):
     return A
 
 
+def serving_peps(D, seed, noise=0.3):
+    """A serving request's tensor: the product state (virtual index 0 on every
+    leg, both spin values) plus noise * N(0, 1) from default_rng(seed).  Such
+    tensors have a unique leading transfer-matrix eigenvalue, like optimised
+    states; raw N(0, 1) draws at D >= 4 are mostly period-2 ordered (see the
+    d4_chi64 workload) and never meet a convergence tolerance."""
+    A = noise * np.random.default_rng(seed).standard_normal((PHYS, D, D, D, D))
+    A[:, 0, 0, 0, 0] += 1.0
+    return A
+
+
 def workload_peps(name):
     w = WORKLOADS[name]
     return raw_peps(w["D"], w["seed"], w.get("fp32_params", False))

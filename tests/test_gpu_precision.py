@@ -92,7 +92,13 @@ def test_fp32_form_d4_chi64_vs_stored_oracle():
     """The FP32 workload (beta = 0.2216, D = 4, chi = 64) run until its FP32
     phase ends (spectrum change below 1e-6, no FP64 refinement), against the
     FP64 oracle converged to tol 1e-9, stored by tests/golden/make_reference.py
-    (d4_chi64_conv.npz).  Bars: f relative 1e-6, g relative l2 1e-4."""
+    (d4_chi64_conv.npz).  Bar: f relative 5e-6, the sum of two parts.  The
+    phase stops one move after the spectrum changes by less than 1e-6; the
+    FP64 run contracts by about 0.45 per move here (25 moves to 1e-9), so the
+    environment is left about 1e-6 from its fixed point and f, first order in
+    it, as far.  FP32 rounding in a contraction over K = chi D^2 = 1024 terms
+    adds about sqrt(K) 2^-24 = 2e-6.  (The gradient of an environment converged
+    only to the FP32 floor is checked after the refinement, below.)"""
     path = os.path.join(GOLDEN, "d4_chi64_conv.npz")
     if not os.path.exists(path):
         pytest.skip("stored oracle reference not generated")
@@ -104,14 +110,13 @@ def test_fp32_form_d4_chi64_vs_stored_oracle():
         done, delta, conv = c.iterate(0)
         assert conv, (done, delta)
         f, _, _ = c.free_energy()
-        g = c.grad()
-    assert rel(f, float(ref["f"])) <= 1e-6, (f, float(ref["f"]))
-    assert np.linalg.norm(g - ref["g"]) <= 1e-4 * np.linalg.norm(ref["g"])
+    assert rel(f, float(ref["f"])) <= 5e-6, (f, float(ref["f"]))
 
 
 def test_fp32_form_with_refinement_d4_chi64_vs_stored_oracle():
     """The same workload with the FP64 refinement after the FP32 phase, to
-    tol 1e-9: f relative 1e-9 against the converged FP64 oracle."""
+    tol 1e-9: f relative 1e-9 and g relative l2 1e-6 against the converged
+    FP64 oracle."""
     path = os.path.join(GOLDEN, "d4_chi64_conv.npz")
     if not os.path.exists(path):
         pytest.skip("stored oracle reference not generated")
@@ -122,7 +127,9 @@ def test_fp32_form_with_refinement_d4_chi64_vs_stored_oracle():
         done, delta, conv = c.iterate(0)
         assert conv, (done, delta)
         f, _, _ = c.free_energy()
+        g = c.grad()
     assert rel(f, float(ref["f"])) <= 1e-9, (f, float(ref["f"]))
+    assert np.linalg.norm(g - ref["g"]) <= 1e-6 * np.linalg.norm(ref["g"])
 
 
 def test_reduced_precision_context_reports_fp32_gemm_class():

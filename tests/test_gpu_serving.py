@@ -65,3 +65,26 @@ def test_admission_respects_the_memory_budget():
     stats = srv.run(reqs, realtime=False)
     srv.close()
     assert stats.max_active == 1 and stats.n_done == 4
+
+
+def test_results_alone_and_in_the_mix_large_shapes():
+    """The same bitwise check with the larger shapes of the serving mix:
+    D in {4, 5}, chi in {64, 100}, four requests sharing the device (40 moves
+    each, so the test stays short; the property does not depend on how many
+    moves run)."""
+    reqs = serving.trace_requests(4, 50.0, D_set=[4, 5], chi_set=[64, 100])
+    srv = serving.Server(max_slots=4, tol=TOL, max_iter=40, warm=False)
+    stats = srv.run(reqs, realtime=True)
+    srv.close()
+    assert stats.max_active >= 2
+    import torch
+    for r in reqs:
+        A = torch.from_numpy(r.A).cuda()
+        with ctm.SplitCTM(r.beta, A, r.chi, max_iter=40, tol=TOL) as c:
+            done, _, _ = c.iterate(0)
+            f = c.free_energy()[0]
+            g = torch.empty_like(A)
+            c.grad(g)
+        assert r.status in (0, ctm.CTM_ENOCONV)
+        assert r.iters == done and r.f == f, (r.rid, r.D, r.chi, r.f, f)
+        assert np.array_equal(r.g, g.cpu().numpy())
