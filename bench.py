@@ -223,6 +223,7 @@ def main():
         print("profile pass" + " (%.0f s)" % (time.perf_counter() - T_START), file=sys.stderr, flush=True)
         c, pinfo = gpu_eval(ctm, torch, w, A, g, sp, profile=True)
         stats = {k: c.kernel_stats(k) for k in KERNEL_CLASSES}
+        fac = c.kernel_stats(5)          # the factorisations' share of class 0
         c.close()
         total_ms = sum(v[1] for v in stats.values())
         dom = max((k for k in stats if KERNEL_CLASSES[k][2] is not None), key=lambda k: stats[k][1])
@@ -239,6 +240,17 @@ def main():
                         classes={KERNEL_CLASSES[k][0]: dict(launches=v[0], ms=v[1],
                                                             tflops=(v[2] / (v[1] / 1e3) / 1e12) if v[1] > 0 and v[2] > 0 else None)
                                  for k, v in stats.items()})
+        # class 0 split into the contraction products (absorption, projector
+        # environments, renormalisation, f and g) and the factorisations'
+        # products (subspace iteration, Cholesky QR, Rayleigh-Ritz, projector
+        # assembly)
+        con = tuple(a - b for a, b in zip(stats[0], fac))
+        split = {}
+        for key, v in (("contraction", con), ("factorisation", fac)):
+            tf = v[2] / (v[1] / 1e3) / 1e12 if v[1] > 0 else None
+            split[key] = dict(launches=int(v[0]), ms=v[1], flops_per_launch=v[2] / max(v[0], 1),
+                              tflops=tf, frac=(tf / PEAK_FP64_MFMA_TFLOPS) if tf is not None else None)
+        roofline["fp64_gemm_split"] = split
 
     fp32 = None
     if not args.no_fp32_leg:

@@ -224,7 +224,11 @@ ctm_status ctm_energy(ctm_ctx* c, double* u);
 
 /* Launch statistics of a context built with CTM_FLAG_PROFILE: which = 0 the
  * FP64 MFMA GEMM kernel, 1 the Jacobi SVD kernels, 2 the Cholesky QR kernels,
- * 3 the FP32 / BF16 MFMA GEMM kernel, 4 the split-K reduction of the GEMMs.
+ * 3 the FP32 / BF16 MFMA GEMM kernel, 4 the split-K reduction of the GEMMs,
+ * 5 the part of class 0 issued by the factorisations (subspace iteration,
+ * Cholesky-QR Gram and triangular products, Rayleigh-Ritz, projector
+ * assembly P_B = rho_T V S^-1/2, P_T = S^-1/2 U^T rho_B); class 0 minus
+ * class 5 are the contraction products.
  * launches, summed kernel time in ms (HIP events on the context's streams
  * around each launch; the two network streams may overlap) and algorithmic
  * flops: 2 M N K per GEMM; per Jacobi sweep and column pair 12 m (+ 6 n with

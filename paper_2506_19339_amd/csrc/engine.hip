@@ -210,6 +210,7 @@ struct KStat {
     double bytes = 0.0;              // algorithmic operand + result bytes
     double ms = 0.0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    bool owns_events = true;         // false: the events belong to another class
 };
 
 constexpr int kJacobiExact = 64;    // exact Jacobi SVD when min(m, n) <= this
@@ -286,8 +287,16 @@ struct Worker {
     double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
     int cur = CTM_FP64;              // precision of the GEMMs issued now
     bool profiling = false;
-    KStat kstat[5];                  // [0] FP64 GEMM, [1] Jacobi SVD, [2] Cholesky QR, [3] FP32/BF16 GEMM,
-                                     // [4] split-K reduction
+    KStat kstat[6];                  // [0] FP64 GEMM, [1] Jacobi SVD, [2] Cholesky QR, [3] FP32/BF16 GEMM,
+                                     // [4] split-K reduction, [5] the part of [0] issued by the
+                                     // factorisations (subspace iteration, Cholesky QR, Rayleigh-Ritz,
+                                     // projector assembly; shares [0]'s events)
+    int factor_depth = 0;            // > 0 while a factorisation issues GEMMs
+    struct FactorScope {
+        Worker& w;
+        explicit FactorScope(Worker& x) : w(x) { ++w.factor_depth; }
+        ~FactorScope() { --w.factor_depth; }
+    };
     std::vector<hipEvent_t> ev_pool;
     // profile mode: sweeps of every Jacobi job, for its algorithmic flop count
     static constexpr int kSweepSlots = 4096;
@@ -301,6 +310,7 @@ struct Worker {
         D = d_bond;
         A = a;
         profiling = (c.flags & CTM_FLAG_PROFILE) != 0;
+        kstat[5].owns_events = false;
         reduced = (c.flags & CTM_FLAG_REDUCED) != 0;
         full_p4 = (c.flags & CTM_FLAG_FULL_P4) != 0;
         // the reduced method's enlarged corner (chi D^2 d wide, cut in a flat
@@ -324,10 +334,11 @@ struct Worker {
         for (void* p : owned) (void)hipFree(p);
         owned.clear();
         for (auto& k : kstat) {
-            for (auto& pr : k.pending) {
-                (void)hipEventDestroy(pr.first);
-                (void)hipEventDestroy(pr.second);
-            }
+            if (k.owns_events)
+                for (auto& pr : k.pending) {
+                    (void)hipEventDestroy(pr.first);
+                    (void)hipEventDestroy(pr.second);
+                }
             k.pending.clear();
         }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -425,6 +436,7 @@ struct Worker {
                 float t = 0.f;
                 HIPCHK(hipEventElapsedTime(&t, pr.first, pr.second));
                 k.ms += t;
+                if (!k.owns_events) continue;
                 ev_pool.push_back(pr.first);
                 ev_pool.push_back(pr.second);
             }
@@ -459,6 +471,12 @@ struct Worker {
         kstat[cls].flops += flops;
         kstat[cls].bytes += bytes;
         kstat[cls].pending.push_back({e, mid});
+        if (cls == 0 && factor_depth > 0) {
+            kstat[5].launches += 1;
+            kstat[5].flops += flops;
+            kstat[5].bytes += bytes;
+            kstat[5].pending.push_back({e, mid});
+        }
         hipEvent_t end = ev_get();
         HIPCHK(hipEventRecord(end, st));
         if (split) kstat[4].launches += 1;
@@ -890,6 +908,7 @@ struct Worker {
     // power: power steps of the subspace iteration (0: the schedule below)
     void svd_batch(std::vector<SvdReq>& rq, int power = 0)
     {
+        FactorScope fs(*this);
         Prec fp64(*this, CTM_FP64);   // factorisations stay FP64 in every precision form
         std::vector<JReq> ex;
         std::vector<size_t> ex_of, rnd;
@@ -1034,6 +1053,7 @@ struct Worker {
     std::vector<Projector> projectors(const std::vector<std::pair<Tn, Tn>>& prs, int64_t chi, int slot0,
                                       bool fill = false)
     {
+        FactorScope fs(*this);
         REQUIRE(prs.size() <= (size_t)kMaxBatch, "too many projectors in one batch");
         std::vector<Projector> out(prs.size());
         std::vector<SvdReq> rq;
@@ -2335,7 +2355,7 @@ ctm_status ctm_query(const ctm_ctx* c, int* total_iters, long long* device_bytes
 ctm_status ctm_kernel_stats(ctm_ctx* c, int which, long long* launches, double* ms, double* flops,
                             double* bytes)
 {
-    if (!c || which < 0 || which > 4) return CTM_EINVAL;
+    if (!c || which < 0 || which > 5) return CTM_EINVAL;
     if (!(c->cfg.flags & CTM_FLAG_PROFILE)) { c->err = "context not built with CTM_FLAG_PROFILE"; return CTM_ESTATE; }
     return guarded(c, [&] {
         long long l = 0;

@@ -223,7 +223,8 @@ class SplitCTM:
     def kernel_stats(self, which):
         """(launches, total ms, algorithmic flops, algorithmic bytes) of kernel
         class which (0 FP64 GEMM, 1 Jacobi, 2 Cholesky QR, 3 FP32/BF16 GEMM,
-        4 split-K reduction) of a context built with profile=True."""
+        4 split-K reduction, 5 the factorisations' part of class 0) of a
+        context built with profile=True."""
         n = ctypes.c_longlong(0)
         ms = ctypes.c_double(0.0)
         fl = ctypes.c_double(0.0)

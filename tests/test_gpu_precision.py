@@ -141,3 +141,17 @@ def test_reduced_precision_context_reports_fp32_gemm_class():
         n64, _, _, _ = c.kernel_stats(0)
         n32, _, fl32, by32 = c.kernel_stats(3)
     assert n32 > 0 and fl32 > 0 and by32 > 0
+
+
+def test_factorisation_gemms_are_a_subset_of_the_fp64_class():
+    """Class 5 counts the FP64 GEMMs issued by the factorisations: a part of
+    class 0, non-empty once a move truncates, with its own event times."""
+    A = raw_peps(3, 0)
+    with ctm.SplitCTM(0.2, A, 20, profile=True) as c:
+        c.iterate(6)
+        n0, ms0, fl0, by0 = c.kernel_stats(0)
+        n5, ms5, fl5, by5 = c.kernel_stats(5)
+        with pytest.raises(ctm.CtmError):
+            c.kernel_stats(6)
+    assert 0 < n5 < n0 and 0 < fl5 < fl0 and 0 < by5 < by0
+    assert 0 < ms5 < ms0
