@@ -44,20 +44,24 @@ KERNEL_CLASSES = {
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d5_chi100_traffic.json")
 KERNELS_SRC = os.path.join(ROOT, "paper_2506_19339_amd", "csrc", "kernels.hip")
+ENGINE_SRC = os.path.join(ROOT, "paper_2506_19339_amd", "csrc", "engine.hip")
 TRAFFIC_KEY = {0: "gemm_f64_kernel", 1: "jacobi_reg_kernel", 2: "cholqr_reg_kernel"}
 
 
 def measured_traffic(cls):
     """HBM bytes per launch of the kernel class from the FETCH_SIZE / WRITE_SIZE
     counter runs recorded in profiles/ (scaled by the copy calibration), or
-    None when they were taken with other kernel source than the current one."""
+    None when they were taken with other kernel or engine source than the
+    current one (the engine decides which products are launched)."""
     import hashlib
     try:
         data = json.load(open(TRAFFIC_FILE))
-        cur = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+        cur_k = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+        cur_e = hashlib.sha256(open(ENGINE_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
-    if data.get("kernels_hip_sha256") != cur or TRAFFIC_KEY.get(cls) not in data["kernels"]:
+    if (data.get("kernels_hip_sha256") != cur_k or data.get("engine_hip_sha256") != cur_e
+            or TRAFFIC_KEY.get(cls) not in data["kernels"]):
         return None
     return data["kernels"][TRAFFIC_KEY[cls]]["hbm_bytes_per_launch"]
 
