@@ -27,6 +27,11 @@ WORKLOADS = {
                      svd_cutoff=1e-8),
     "d5_chi100": dict(beta=0.22, D=5, chi=100, max_iter=200, tol=1e-9, prec="fp64", seed=0,
                       fp32_params=True, svd_cutoff=1e-8),
+    # the D = 4 tensor at chi = 128: the Rayleigh-Ritz cores (144) exceed the
+    # 128 of the register kernels, as at D = 6, chi = 144, at a size the
+    # oracle can run to convergence (BF16 + FP64 refinement parity)
+    "d4_chi128": dict(beta=0.2216, D=4, chi=128, max_iter=200, tol=1e-9, prec="bf16", seed=8,
+                      svd_cutoff=1e-8),
     # seed 1: the triple-layer network of the D = 6 draw with seed 0 is period-2
     # ordered (see d4_chi64)
     "d6_chi144": dict(beta=0.22, D=6, chi=144, max_iter=200, tol=1e-9, prec="bf16", seed=1,

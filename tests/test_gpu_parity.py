@@ -189,6 +189,32 @@ def test_d5_chi100_converged_against_stored_oracle_reference():
     assert np.max(np.abs(g - go)) <= 1e-8 * np.max(np.abs(go)), np.max(np.abs(g - go)) / np.max(np.abs(go))
 
 
+def test_d4_chi128_converged_against_stored_oracle_reference():
+    """FP64 at D = 4, chi = 128 run to convergence (tol 1e-9) against
+    tests/golden/d4_chi128_conv.npz (the oracle converged the same way): the
+    bases of the subspace factorisation are 144 rows, orthonormalised by
+    block Gram-Schmidt, and the cores run the LDS Jacobi.  Bars as for
+    D = 5, chi = 100: f and ln kappa 1e-10, g element-wise 1e-8 of max|g|."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "d4_chi128_conv.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle reference not generated")
+    ref = np.load(path)
+    w = WORKLOADS["d4_chi128"]
+    from synth_inputs import workload_peps
+    with ctm.SplitCTM(w["beta"], workload_peps("d4_chi128"), w["chi"], max_iter=w["max_iter"], tol=w["tol"],
+                      svd_cutoff=float(ref["svd_cutoff"])) as c:
+        done, delta, conv = c.iterate(0)
+        assert conv, (done, delta)
+        f, l3, l2 = c.free_energy()
+        g = c.grad()
+    fo, l3o, l2o, go = float(ref["f"]), float(ref["log_kappa3"]), float(ref["log_kappa2"]), ref["g"]
+    print("moves", done, "oracle", int(ref["iters"]), "f", f, fo)
+    assert abs(l3 - l3o) <= 1e-10 * abs(l3o) and abs(l2 - l2o) <= 1e-10 * abs(l2o), (l3, l3o, l2, l2o)
+    assert abs(f - fo) <= 1e-10 * abs(fo), (f, fo)
+    assert np.max(np.abs(g - go)) <= 1e-8 * np.max(np.abs(go)), np.max(np.abs(g - go)) / np.max(np.abs(go))
+
+
 def test_d6_chi144_against_stored_oracle_reference():
     """The shape of the low-precision workload (beta = 0.22, D = 6, chi = 144),
     here in FP64 at the shipped factorisation defaults, after 6 iterations

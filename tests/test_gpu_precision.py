@@ -155,3 +155,25 @@ def test_factorisation_gemms_are_a_subset_of_the_fp64_class():
             c.kernel_stats(6)
     assert 0 < n5 < n0 and 0 < fl5 < fl0 and 0 < by5 < by0
     assert 0 < ms5 < ms0
+
+
+def test_bf16_refinement_large_cores_vs_stored_oracle():
+    """BF16 + FP64 refinement at D = 4, chi = 128 (beta = 0.2216): the
+    Rayleigh-Ritz cores are 144 wide, above the 128 of the register kernels,
+    as in the BF16 workload at D = 6, chi = 144 (block Gram-Schmidt bases,
+    LDS Jacobi, the thin power schedule), at a size whose converged oracle run
+    is stored (d4_chi128_conv.npz, tests/golden/make_reference.py).  Bar:
+    1e-5 relative on f and on the l2 norm of g, the BF16 form's tolerance."""
+    path = os.path.join(GOLDEN, "d4_chi128_conv.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle reference not generated")
+    ref = np.load(path)
+    w = WORKLOADS["d4_chi128"]
+    with ctm.SplitCTM(w["beta"], workload_peps("d4_chi128"), w["chi"], max_iter=w["max_iter"], tol=w["tol"],
+                      precision=ctm.CTM_BF16, refine=True, svd_cutoff=float(ref["svd_cutoff"])) as c:
+        done, delta, conv = c.iterate(0)
+        assert conv, (done, delta)
+        f, _, _ = c.free_energy()
+        g = c.grad()
+    assert rel(f, float(ref["f"])) <= 1e-5, (f, float(ref["f"]))
+    assert np.linalg.norm(g - ref["g"]) <= 1e-5 * np.linalg.norm(ref["g"])
