@@ -1305,6 +1305,12 @@ __device__ inline void rotate_pair(double* __restrict__ xp, double* __restrict__
     }
 }
 
+// A sweep whose rotations all had gamma^2 / (alpha beta) below this (cosines
+// below 1e-8) is the last: cyclic Jacobi converges quadratically, so the
+// columns are then orthogonal to ~1e-16 relative, and the sweep that would
+// follow only confirms it.  (1e-20, the earlier bound, ran that sweep.)
+constexpr float kJacobiDone = 1e-16f;
+
 // XL / WL: X / W live in LDS (decided per batch on the host, so that every
 // access compiles to LDS or global instructions instead of flat ones).
 template <bool XL, bool WL>
@@ -1324,6 +1330,7 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
     const int ngroups = nthr / G;
     const int gid = threadIdx.x / G, gl = threadIdx.x % G;
     __shared__ int rotated;
+    __shared__ unsigned int maxr;                  // largest (gamma^2 / alpha beta) of the sweep, float bits
     __shared__ double sig[1024];
     __shared__ int rnk[1024];
 
@@ -1354,7 +1361,10 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
 
     const double tol = 2.0 * sqrt((double)m) * 2.220446049250313e-16;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (threadIdx.x == 0) rotated = 0;
+        if (threadIdx.x == 0) {
+            rotated = 0;
+            maxr = 0u;
+        }
         __syncthreads();
         for (int step = 0; step < ne - 1; ++step) {
             for (int pi = gid; pi < npairs; pi += ngroups) {
@@ -1383,12 +1393,15 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
                     const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
                     rotate_pair(xp, xq, m, gl, G, c, sn);
                     if (acc_v) rotate_pair(W + (int64_t)p * n, W + (int64_t)q * n, n, gl, G, c, sn);
-                    if (gl == 0) rotated = 1;
+                    if (gl == 0) {
+                        rotated = 1;
+                        atomicMax(&maxr, __float_as_uint((float)(ga * ga / (al * be))));
+                    }
                 }
             }
             __syncthreads();
         }
-        if (rotated == 0) {
+        if (rotated == 0 || __uint_as_float(maxr) < kJacobiDone) {
             if (jb.sweeps && threadIdx.x == 0) jb.sweeps[0] = sweep + 1;
             break;
         }
@@ -1791,9 +1804,8 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
         }
         __syncthreads();
         // done when no pair rotated, or when every rotation of this sweep was
-        // below 1e-10 (then the pairs are orthogonal to ~1e-20 after it, below
-        // the rotation threshold, and a further sweep would rotate nothing)
-        if (rotated == 0 || __uint_as_float(maxr) < 1e-20f) {
+        // below kJacobiDone (see there)
+        if (rotated == 0 || __uint_as_float(maxr) < kJacobiDone) {
             if (jb.sweeps && tid == 0) jb.sweeps[0] = sweep + 1;
             break;
         }
