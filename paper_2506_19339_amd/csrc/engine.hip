@@ -220,6 +220,8 @@ constexpr int kWarmPowerIters = 4;  // power steps when every subspace starts fr
                                     // (the iteration continues across moves).  At D = 5, chi = 100
                                     // the converged f is 2.7e-10 from the oracle's with 2 steps,
                                     // 7e-12 with 4 (6 % more time), 3e-13 with 8 (19 %)
+constexpr int kWarmPowerItersEarly = 2;  // ... while the spectrum still moves by more than
+constexpr double kWarmTight = 1e-6;      // kWarmTight per move (the state is not final yet)
 constexpr int kColdPowerIters = 10; // power steps from random normals
 // the same when the Rayleigh-Ritz core is less than 1.25 kk wide (kk > 112):
 // at D = 6, chi = 144 (core 160) ten cold steps resolve the early moves'
@@ -987,7 +989,9 @@ struct Worker {
         for (size_t j = 0; j < nr; ++j) thin = thin || 4 * Pt[j].d[0] < 5 * rq[rnd[j]].kk;
         const int q = power > 0 ? power
                     : (cfg.power_iters > 0 ? cfg.power_iters
-                                           : (all_warm ? (thin ? kWarmPowerItersThin : kWarmPowerIters)
+                                           : (all_warm ? (thin ? kWarmPowerItersThin
+                                                               : (last_delta < kWarmTight ? kWarmPowerIters
+                                                                                          : kWarmPowerItersEarly))
                                                        : (thin ? kColdPowerItersThin : kColdPowerIters)));
         std::vector<Tn> Ms(nr);
         for (size_t j = 0; j < nr; ++j) Ms[j] = rq[rnd[j]].M;
