@@ -157,3 +157,18 @@ def test_reduced_d5_chi100_vs_stored_oracle():
 def test_reduced_rejects_reduced_precision():
     with pytest.raises(ctm.CtmError):
         ctm.SplitCTM(0.2, raw_peps(2, 0), 8, precision=ctm.CTM_FP32, method="reduced")
+
+
+@pytest.mark.parametrize("D", [5, 6])
+def test_split_holds_less_device_memory_than_the_reduced_method(D):
+    """Sec. III C: the split scheme's environment costs O(chi^2 D^3 d^2) memory
+    against the reduced method's O(chi^2 D^4 d^2) enlarged corner.  Device
+    bytes of a context (ctm_query: arena high-water mark + workspaces, both
+    networks) after three moves at chi = 100, the first two truncating."""
+    A = torch.from_numpy(raw_peps(D, 0)).cuda()
+    held = {}
+    for method in ("split", "reduced"):
+        with ctm.SplitCTM(0.22, A, 100, max_iter=3, tol=0.0, method=method) as c:
+            c.iterate(3)
+            held[method] = c.query()[1]
+    assert held["split"] < held["reduced"], held
