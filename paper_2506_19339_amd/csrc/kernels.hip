@@ -235,12 +235,62 @@ int gemm_split_plan(int M, int N, int K, int batch, int64_t ws_cap)
     return std::max(s, 1);
 }
 
+// Long, skinny products with a short contraction (A M x K and B K x N, both
+// untransposed, N at most 8, K at most kSkinnyMax): the absorption of the
+// PEPO into an environment tensor (M up to ~1e6, N = K = 2 ... 8).  The
+// 64-wide MFMA tiles would be mostly padding here and the product is
+// HBM-bound (8 (M K + M N) bytes for 2 M N K flops).  One thread per row (the
+// kernel also takes wider N in groups of 8 columns, but from N = 25 on the
+// MFMA tile kernel is faster: its output tiles are written coalesced); B is
+// staged in LDS and read by broadcast.  M = 1.25e6, N = K = 8: 57 us against
+// 236 us in the tile kernel.
+constexpr int kSkinnyMax = 64;
+constexpr int kSkinnyCols = 8;
+
+__global__ __launch_bounds__(256) void gemm_skinny_kernel(int M, int N, int K, double alpha,
+                                                          const double* __restrict__ A, int64_t lda,
+                                                          const double* __restrict__ B, int64_t ldb, double beta,
+                                                          double* __restrict__ C, int64_t ldc)
+{
+    __shared__ double Bs[kSkinnyMax * kSkinnyMax];
+    for (int e = threadIdx.x; e < K * N; e += blockDim.x) Bs[e] = B[(int64_t)(e / N) * ldb + (e % N)];
+    __syncthreads();
+    const int nch = (N + kSkinnyCols - 1) / kSkinnyCols;
+    const int rows = (int)blockDim.x / nch;
+    const int r = (int)threadIdx.x / nch, ch = (int)threadIdx.x % nch;
+    const int64_t m = (int64_t)blockIdx.x * rows + r;
+    if (r >= rows || m >= M) return;
+    const int n0 = ch * kSkinnyCols;
+    double acc[kSkinnyCols];
+#pragma unroll
+    for (int j = 0; j < kSkinnyCols; ++j) acc[j] = 0.0;
+    const double* a = A + m * lda;
+    for (int k = 0; k < K; ++k) {
+        const double av = a[k];
+        const double* b = Bs + k * N + n0;
+#pragma unroll
+        for (int j = 0; j < kSkinnyCols; ++j)
+            if (n0 + j < N) acc[j] += av * b[j];
+    }
+    double* c = C + m * ldc + n0;
+#pragma unroll
+    for (int j = 0; j < kSkinnyCols; ++j)
+        if (n0 + j < N) c[j] = beta == 0.0 ? alpha * acc[j] : alpha * acc[j] + beta * c[j];
+}
+
 void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
               const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
               double beta, double* C, int64_t ldc, int64_t sC, int batch, double* ws, int64_t ws_cap,
               hipEvent_t mid)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return;
+    if (!ta && !tb && batch == 1 && K >= 1 && N <= kSkinnyCols && K <= kSkinnyMax && (int64_t)M * N >= (1 << 16)) {
+        const int rows = 256 / ((N + kSkinnyCols - 1) / kSkinnyCols);
+        hipLaunchKernelGGL(gemm_skinny_kernel, dim3((unsigned)((M + rows - 1) / rows)), dim3(256), 0, s, M, N, K,
+                           alpha, A, lda, B, ldb, beta, C, ldc);
+        if (mid) (void)hipEventRecord(mid, s);
+        return;
+    }
     int ksplit = (beta == 0.0 && ws) ? gemm_split_plan(M, N, K, batch, ws_cap) : 1;
     int kchunk = K;
     if (ksplit > 1) {

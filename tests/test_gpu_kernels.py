@@ -45,6 +45,15 @@ def test_gemm_matches_numpy(lib, ta, tb, M, N, K, batch):
     _gemm_case(lib, ta, tb, M, N, K, batch, 0)
 
 
+@pytest.mark.parametrize("M,N,K", [(65536, 1, 1), (250000, 2, 2), (250000, 4, 1), (65537, 8, 8), (9000, 8, 64),
+                                   (1250000, 8, 8), (40000, 25, 50), (70000, 9, 3)])
+def test_gemm_skinny_short_k_matches_numpy(lib, M, N, K):
+    """Long products with N <= 8, K <= 64 (A, B untransposed, M N >= 65536)
+    take the skinny kernel (one thread per row, B in LDS); rows per block that
+    do not divide M included, and wider N (tile kernel) beside them."""
+    _gemm_case(lib, 0, 0, M, N, K, 1, 0)
+
+
 def _gemm_case(lib, ta, tb, M, N, K, batch, ws_cap):
     rng = np.random.default_rng(M * 7 + N + K)
     A = rng.standard_normal((batch, K, M) if ta else (batch, M, K))
