@@ -542,6 +542,15 @@ void gemm_lp(hipStream_t s, int prec, bool ta, bool tb, int M, int N, int K, dou
              hipEvent_t mid)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return;
+    if (!ta && !tb && batch == 1 && K >= 1 && N <= kSkinnyCols && K <= kSkinnyMax && (int64_t)M * N >= (1 << 16)) {
+        // HBM-bound: the FP64 skinny kernel moves the same bytes as an FP32
+        // product would (operands and result are FP64 in memory)
+        const int rows = 256 / ((N + kSkinnyCols - 1) / kSkinnyCols);
+        hipLaunchKernelGGL(gemm_skinny_kernel, dim3((unsigned)((M + rows - 1) / rows)), dim3(256), 0, s, M, N, K,
+                           alpha, A, lda, B, ldb, beta, C, ldc);
+        if (mid) (void)hipEventRecord(mid, s);
+        return;
+    }
     int ksplit = (beta == 0.0 && ws) ? gemm_split_plan(M, N, K, batch, ws_cap) : 1;
     int kchunk = K;
     if (ksplit > 1) {
