@@ -246,9 +246,11 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--budget-gib", type=float, default=200.0)
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=200, help="moves per request at most")
     args = ap.parse_args()
     reqs = trace_requests(args.requests, args.rate)
-    srv = Server(hbm_budget=args.budget_gib * GiB, max_slots=args.slots, warm=not args.no_warm)
+    srv = Server(hbm_budget=args.budget_gib * GiB, max_slots=args.slots, warm=not args.no_warm,
+                 max_iter=args.max_iter)
     done = [0]
 
     def progress(req):
