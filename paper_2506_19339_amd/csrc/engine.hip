@@ -82,6 +82,16 @@ public:
 
     Mark mark() const { return {cur_, off_}; }
     void release(Mark m) { cur_ = m.cur; off_ = m.off; }
+    // order of an address inside the arena (chunk, offset), -1 outside it
+    int64_t key_of(const void* p) const
+    {
+        for (size_t c = 0; c < ch_.size(); ++c) {
+            const char* b = ch_[c].p;
+            if ((const char*)p >= b && (const char*)p < b + ch_[c].cap)
+                return ((int64_t)c << 40) + (int64_t)((const char*)p - b);
+        }
+        return -1;
+    }
 
     // fixed-buffer mode (the allocation-free entry point): every allocation
     // comes from [p, p + cap); running out raises CTM_ENOMEM instead of
@@ -596,28 +606,57 @@ struct Worker {
 
     // Keeps the listed tensors and returns everything else allocated since m
     // to the arena, so that a chain of contractions holds its intermediates
-    // only while it runs.  Each kept tensor is copied above the arena's top
-    // first and then down from m: a bump allocator places a subset of its
-    // earlier allocations no higher than they were, so neither copy overlaps
-    // its source.  Not used while work is on the side stream.
+    // only while it runs.  The distinct buffers of the kept tensors are copied
+    // above the arena's top, in arena order, and then down from m: a bump
+    // allocator places a subset of its earlier allocations, taken in order,
+    // no higher than they were, so no copy overlaps its source.  Should a
+    // placement still reach a copy above the top (chunk boundaries), the
+    // tensors stay in their copies above the top instead.  Not used while
+    // work is on the side stream.
     void settle(Arena::Mark m, std::initializer_list<Tn*> keep)
     {
         REQUIRE(!on_side, "settle during side work");
-        double* up[8];
-        int n = 0;
         REQUIRE(keep.size() <= 8, "settle: too many tensors");
+        struct Buf {
+            double* src;
+            int64_t n, key;
+            double *up, *q;
+        };
+        Buf b[8];
+        int nb = 0;
         for (Tn* t : keep) {
-            up[n] = ws.alloc(t->n());
-            ctmk::copy(st, t->p, up[n], t->n());
-            ++n;
+            int j = 0;
+            while (j < nb && b[j].src != t->p) ++j;
+            if (j == nb) b[nb++] = Buf{t->p, t->n(), ws.key_of(t->p), nullptr, nullptr};
+            else b[j].n = std::max(b[j].n, t->n());
         }
+        std::sort(b, b + nb, [](const Buf& x, const Buf& y) { return x.key < y.key; });
+        for (int j = 0; j < nb; ++j) {
+            b[j].up = ws.alloc(b[j].n);
+            ctmk::copy(st, b[j].src, b[j].up, b[j].n);
+        }
+        const Arena::Mark above = ws.mark();
         ws.release(m);
-        n = 0;
-        for (Tn* t : keep) {
-            double* q = ws.alloc(t->n());
-            ctmk::copy(st, up[n++], q, t->n());
-            t->p = q;
+        bool ok = true;
+        for (int j = 0; j < nb && ok; ++j) {
+            double* q = ws.alloc(b[j].n);
+            for (int i = 0; i < nb; ++i)
+                if (q < b[i].up + b[i].n && b[i].up < q + b[j].n) ok = false;
+            if (ok) {
+                ctmk::copy(st, b[j].up, q, b[j].n);
+                b[j].q = q;
+            }
         }
+        if (!ok) {
+            ws.release(above);
+            for (int j = 0; j < nb; ++j) b[j].q = b[j].up;
+        }
+        for (Tn* t : keep)
+            for (int j = 0; j < nb; ++j)
+                if (b[j].src == t->p) {
+                    t->p = b[j].q;
+                    break;
+                }
     }
 
     // ctr("ab,bc->ac", A, B): labelled pairwise contraction.  Labels shared by
