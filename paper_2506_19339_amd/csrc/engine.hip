@@ -247,6 +247,7 @@ constexpr int64_t kCoreMax = 128;   // largest Rayleigh-Ritz core (register-resi
 // it resolves in FP64.
 constexpr double kDefaultCutoff = 1e-8;
 constexpr int kJacobiSweeps = 40;
+constexpr int kWarmJacobiSweeps = 3;   // Rayleigh-Ritz core sweeps of a settling warm move
 constexpr int64_t kCholRegRows = 128;  // rows of the register-resident Cholesky-QR kernel
 constexpr int kFillPowerIters = 40; // power steps of the growth-phase Gram factorisations
 constexpr int kMaxBatch = 16;       // projectors factorised together
@@ -807,7 +808,7 @@ struct Worker {
         bool want_v;
         Tn U, V, S;
     };
-    void jacobi_batch(std::vector<JReq>& rq)
+    void jacobi_batch(std::vector<JReq>& rq, int max_sweeps = kJacobiSweeps)
     {
         for (size_t b0 = 0; b0 < rq.size(); b0 += ctmk::kMaxJacobiBatch) {
             ctmk::JacobiBatch jb{};
@@ -837,7 +838,7 @@ struct Worker {
                     j.X = X.p;
                 }
             hipEvent_t e = prof_begin();
-            ctmk::jacobi_svd(st, jb, kJacobiSweeps);
+            ctmk::jacobi_svd(st, jb, max_sweeps);
             prof_end(1, e, 0.0);
         }
     }
@@ -1053,7 +1054,10 @@ struct Worker {
             // Bs row-major == Bs^T col-major: Bs^T = Uj S Vj^T -> Bs = Vj S Uj^T
             core[j] = JReq{Bs[j].p, k, k, true, {}, {}, {}};
         }
-        jacobi_batch(core);
+        // while a warm iteration is still settling (spectrum change above
+        // kWarmTight) three sweeps of the core suffice: the next move continues
+        // from these Ritz vectors; the final moves converge it fully
+        jacobi_batch(core, (all_warm && last_delta >= kWarmTight) ? kWarmJacobiSweeps : kJacobiSweeps);
         std::vector<Tn> Vjt(nr), Ujt(nr);
         for (size_t j = 0; j < nr; ++j) {
             const int64_t k = core[j].S.d[0];
