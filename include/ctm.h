@@ -177,9 +177,11 @@ ctm_status ctm_free_energy_noalloc(ctm_ctx* c, double* f, double* log_kappa3, do
  * the layout of A (host or device per CTM_FLAG_DEVICE_PTRS). */
 ctm_status ctm_grad(ctm_ctx* c, double* g);
 
-/* Singular values of C1 C2 C3 C4 / |Tr(C1 C2 C3 C4)| for network which = 3
- * (triple layer) or 2 (double layer), descending; *n receives the count
- * (<= cap).  Host buffer. */
+/* Singular values of C1 C2 C3 C4 / |Tr(C1 C2 C3 C4)| of the current
+ * environment for network which = 3 (triple layer) or 2 (double layer),
+ * descending, computed on the call with converged Jacobi sweeps (a move far
+ * from convergence estimates its spectrum change with fewer); *n receives the
+ * count (<= cap).  Host buffer.  Synchronises. */
 ctm_status ctm_corner_spectrum(ctm_ctx* c, int which, double* s, int cap, int* n);
 
 /* Replace beta and A and keep the converged environments as the starting

@@ -1230,6 +1230,9 @@ struct Worker {
     // ---------------- one symmetric split-CTMRG iteration of one network
     void step(Net& N, int64_t chi);
     void values(Net& N, bool with_env);
+    // the corner spectrum of the current environment with converged Jacobi
+    // sweeps into N.s_old / N.n_old (a settling move may have capped them)
+    void exact_spectrum(Net& N);
     // ---------------- the same for the reduced method
     void step_reduced(Net& N, int64_t chi);
     void values_reduced(Net& N, bool with_env);
@@ -1436,7 +1439,10 @@ void Worker::step(Net& N, int64_t chi)
         ctmk::trace(st, R.p, (int)k4, N.sc + 7);
         side_begin();
         std::vector<JReq> sp{JReq{R.p, k4, k4, false, {}, {}, {}}};
-        jacobi_batch(sp);
+        // far from convergence the change only has to be known roughly (it
+        // gates warm starts at 1e-3 and 1e-6): a few sweeps; near it, all
+        // (ctm_corner_spectrum recomputes the spectrum it returns)
+        jacobi_batch(sp, last_delta >= kWarmTight ? kWarmJacobiSweeps : kJacobiSweeps);
         ctmk::spectrum_delta(st, sp[0].S.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
         side_end();
     }
@@ -1469,6 +1475,22 @@ void Worker::step(Net& N, int64_t chi)
     ctmk::copy(st, Tk_n.p, N.Tk, Tk_n.n());
     ctmk::copy(st, Ti_n.p, N.Ti, Ti_n.n());
     ctmk::copy(st, Tb_n.p, N.Tb, Tb_n.n());
+    ws.release(mk);
+}
+
+void Worker::exact_spectrum(Net& N)
+{
+    Prec fp64(*this, CTM_FP64);
+    const Arena::Mark mk = ws.mark();
+    const int64_t k = N.xbk;
+    Tn C1 = make_tn(N.C1, {k, k});
+    Tn C4 = reduced ? C1 : make_tn(N.C4, {k, k});   // reduced method: one corner, C^4
+    Tn R1 = ctr("ab,bc->ac", C1, C4);
+    Tn R = mat(ctr("ab,bc->ac", R1, R1));
+    ctmk::trace(st, R.p, (int)k, N.sc + 7);
+    std::vector<JReq> sp{JReq{R.p, k, k, false, {}, {}, {}}};
+    jacobi_batch(sp, kJacobiSweeps);
+    ctmk::spectrum_delta(st, sp[0].S.p, (int)k, N.sc + 7, N.s_old, N.n_old, scal);   // change not kept
     ws.release(mk);
 }
 
@@ -2360,6 +2382,7 @@ ctm_status ctm_corner_spectrum(ctm_ctx* c, int which, double* s, int cap, int* n
         const int i = which == 3 ? 0 : 1;
         Net& N = c->net[i];
         hipStream_t st = c->w[i].st;
+        c->w[i].exact_spectrum(N);
         int cnt = 0;
         HIPCHK(hipMemcpyAsync(&cnt, N.n_old, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
