@@ -232,7 +232,10 @@ constexpr int kWarmPowerIters = 4;  // power steps when every subspace starts fr
                                     // 7e-12 with 4 (6 % more time), 3e-13 with 8 (19 %)
 constexpr int kWarmPowerItersEarly = 2;  // ... while the spectrum still moves by more than
 constexpr double kWarmTight = 1e-6;      // kWarmTight per move (the state is not final yet)
-constexpr int kColdPowerIters = 10; // power steps from random normals
+constexpr int kColdPowerIters = 6;  // power steps from random normals (the moves before the
+                                    // spectrum change drops below kWarmGate; ten made D = 5,
+                                    // chi = 100 5 % slower at the same converged f)
+constexpr int kColdPowerItersReduced = 10;  // the reduced method starts every move cold
 // the same when the Rayleigh-Ritz core is less than 1.25 kk wide (kk > 112):
 // at D = 6, chi = 144 (core 160) ten cold steps resolve the early moves'
 // projectors to ~1e-6 only (f 2e-5 off the oracle after six moves), forty to
@@ -1032,7 +1035,9 @@ struct Worker {
                                            : (all_warm ? (thin ? kWarmPowerItersThin
                                                                : (last_delta < kWarmTight ? kWarmPowerIters
                                                                                           : kWarmPowerItersEarly))
-                                                       : (thin ? kColdPowerItersThin : kColdPowerIters)));
+                                                       : (thin ? kColdPowerItersThin
+                                                               : (reduced ? kColdPowerItersReduced
+                                                                          : kColdPowerIters))));
         std::vector<Tn> Ms(nr);
         for (size_t j = 0; j < nr; ++j) Ms[j] = rq[rnd[j]].M;
         // a whole last-move Ritz basis has orthonormal rows already
