@@ -232,9 +232,9 @@ constexpr int kWarmPowerIters = 4;  // power steps when every subspace starts fr
                                     // 7e-12 with 4 (6 % more time), 3e-13 with 8 (19 %)
 constexpr int kWarmPowerItersEarly = 2;  // ... while the spectrum still moves by more than
 constexpr double kWarmTight = 1e-6;      // kWarmTight per move (the state is not final yet)
-constexpr int kColdPowerIters = 6;  // power steps from random normals (the moves before the
+constexpr int kColdPowerIters = 4;  // power steps from random normals (the moves before the
                                     // spectrum change drops below kWarmGate; ten made D = 5,
-                                    // chi = 100 5 % slower at the same converged f)
+                                    // chi = 100 7 % slower at the same converged f)
 constexpr int kColdPowerItersReduced = 10;  // the reduced method starts every move cold
 // the same when the Rayleigh-Ritz core is less than 1.25 kk wide (kk > 112):
 // at D = 6, chi = 144 (core 160) ten cold steps resolve the early moves'
@@ -1042,15 +1042,20 @@ struct Worker {
         for (size_t j = 0; j < nr; ++j) Ms[j] = rq[rnd[j]].M;
         // a whole last-move Ritz basis has orthonormal rows already
         if (!all_full) cholqr_pass(Pt);
+        // a settling warm move (spectrum change above kWarmTight) gives its
+        // last bases one Cholesky-QR pass instead of two: the next move
+        // continues from them, and the final moves make them orthonormal
+        const bool loose = all_warm && last_delta >= kWarmTight && !thin;
         for (int it = 0; it < q; ++it) {
             Qt = mm_group(Pt, false, Ms, true);    // (M P)^T
             cholqr_pass(Qt);
             Pt = mm_group(Qt, false, Ms, false);   // (M^T Q)^T
-            if (it + 1 < q) cholqr_pass(Pt);
+            if (it + 1 < q || loose) cholqr_pass(Pt);
             else orth(Pt);
         }
         Qt = mm_group(Pt, false, Ms, true);
-        orth(Qt);
+        if (loose) cholqr_pass(Qt);
+        else orth(Qt);
         const std::vector<Tn> X1 = mm_group(Qt, false, Ms, false);   // Q^T M   (k x n)
         const std::vector<Tn> Bs = mm_group(X1, false, Pt, true);    // Q^T M P (k x k)
         std::vector<JReq> core(nr);
