@@ -1032,9 +1032,8 @@ struct Worker {
         for (size_t j = 0; j < nr; ++j) thin = thin || 4 * Pt[j].d[0] < 5 * rq[rnd[j]].kk;
         const int q = power > 0 ? power
                     : (cfg.power_iters > 0 ? cfg.power_iters
-                                           : (all_warm ? (thin ? kWarmPowerItersThin
-                                                               : (last_delta < kWarmTight ? kWarmPowerIters
-                                                                                          : kWarmPowerItersEarly))
+                                           : (all_warm ? (last_delta >= kWarmTight ? kWarmPowerItersEarly
+                                                               : (thin ? kWarmPowerItersThin : kWarmPowerIters))
                                                        : (thin ? kColdPowerItersThin
                                                                : (reduced ? kColdPowerItersReduced
                                                                           : kColdPowerIters))));
