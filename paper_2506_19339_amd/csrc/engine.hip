@@ -299,6 +299,19 @@ struct Worker {
     bool reduced = false;            // reduced (unsplit) C4v CTMRG on the fused site tensor
     bool full_p4 = false;            // projector 4 from the 2x2 block (default: the half construction)
     double last_delta = 1.0;         // spectrum change of this network's last move (host copy)
+    bool final_phase = false;        // the change has been below kWarmTight: every move runs the
+                                     // factorisations to convergence from then on (no switching
+                                     // back and forth at the threshold)
+    void note_delta(double d)
+    {
+        last_delta = d;
+        if (d < kWarmTight) final_phase = true;
+    }
+    void restart()
+    {
+        last_delta = 1.0;
+        final_phase = false;
+    }
     int bulk = CTM_FP64;             // precision of the bulk contractions in the current phase
     double lp_cut = 0.0;             // testing aid: cutoff of the reduced-precision phase
     int cur = CTM_FP64;              // precision of the GEMMs issued now
@@ -1032,7 +1045,7 @@ struct Worker {
         for (size_t j = 0; j < nr; ++j) thin = thin || 4 * Pt[j].d[0] < 5 * rq[rnd[j]].kk;
         const int q = power > 0 ? power
                     : (cfg.power_iters > 0 ? cfg.power_iters
-                                           : (all_warm ? (last_delta >= kWarmTight ? kWarmPowerItersEarly
+                                           : (all_warm ? (!final_phase ? kWarmPowerItersEarly
                                                                : (thin ? kWarmPowerItersThin : kWarmPowerIters))
                                                        : (thin ? kColdPowerItersThin
                                                                : (reduced ? kColdPowerItersReduced
@@ -1044,7 +1057,7 @@ struct Worker {
         // a settling warm move (spectrum change above kWarmTight) gives its
         // last bases one Cholesky-QR pass instead of two: the next move
         // continues from them, and the final moves make them orthonormal
-        const bool loose = all_warm && last_delta >= kWarmTight && !thin;
+        const bool loose = all_warm && !final_phase && !thin;
         for (int it = 0; it < q; ++it) {
             Qt = mm_group(Pt, false, Ms, true);    // (M P)^T
             cholqr_pass(Qt);
@@ -1066,7 +1079,7 @@ struct Worker {
         // while a warm iteration is still settling (spectrum change above
         // kWarmTight) three sweeps of the core suffice: the next move continues
         // from these Ritz vectors; the final moves converge it fully
-        jacobi_batch(core, (all_warm && last_delta >= kWarmTight) ? kWarmJacobiSweeps : kJacobiSweeps);
+        jacobi_batch(core, (all_warm && !final_phase) ? kWarmJacobiSweeps : kJacobiSweeps);
         std::vector<Tn> Vjt(nr), Ujt(nr);
         for (size_t j = 0; j < nr; ++j) {
             const int64_t k = core[j].S.d[0];
@@ -1451,7 +1464,7 @@ void Worker::step(Net& N, int64_t chi)
         // far from convergence the change only has to be known roughly (it
         // gates warm starts at 1e-3 and 1e-6): a few sweeps; near it, all
         // (ctm_corner_spectrum recomputes the spectrum it returns)
-        jacobi_batch(sp, last_delta >= kWarmTight ? kWarmJacobiSweeps : kJacobiSweeps);
+        jacobi_batch(sp, !final_phase ? kWarmJacobiSweeps : kJacobiSweeps);
         ctmk::spectrum_delta(st, sp[0].S.p, (int)k4, N.sc + 7, N.s_old, N.n_old, N.delta);
         side_end();
     }
@@ -1912,7 +1925,7 @@ static void reset_env(Worker& W, Net& N, int D)
     const int64_t d = N.d;
     N.xbk = N.xki = N.xib = 1;
     N.grown = false;
-    W.last_delta = 1.0;
+    W.restart();
     if (W.reduced)   // product boundary of the fused legs: T[0, m, 0] = 1/sqrt(Df)
         ctmk::fill(W.st, N.Tf, N.Df, 1.0 / std::sqrt((double)N.Df));
     ctmk::fill(W.st, N.C1, 1, 1.0);
@@ -2032,7 +2045,7 @@ static ctm_status iterate_many(ctm_ctx** cs, int n, int n_iter, int* iters_done,
                         HIPCHK(hipMemcpyAsync(&h[wi], c->net[wi].delta, sizeof(double), hipMemcpyDeviceToHost,
                                               c->w[wi].st));
                     sync_workers(c);
-                    for (int wi = 0; wi < 2; ++wi) c->w[wi].last_delta = std::isfinite(h[wi]) ? h[wi] : 1.0;
+                    for (int wi = 0; wi < 2; ++wi) c->w[wi].note_delta(std::isfinite(h[wi]) ? h[wi] : 1.0);
                     dl[i] = std::max(h[0], h[1]);
                     if (!std::isfinite(dl[i])) throw CtmError(CTM_ENUMERIC, "non-finite spectrum");
                     if (until && c->iters > 1) {
@@ -2413,7 +2426,7 @@ ctm_status ctm_reset_tensor(ctm_ctx* c, double beta, const double* A)
         c->join();
         c->lp_done = false;
         c->base_iters = c->iters;
-        for (auto& x : c->w) x.last_delta = 1.0;   // the first move on the new tensor starts cold
+        for (auto& x : c->w) x.restart();   // the first move on the new tensor starts cold
     });
 }
 
