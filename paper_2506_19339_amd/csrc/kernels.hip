@@ -1510,12 +1510,14 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(JacobiBatch jobs, int 
 typedef __attribute__((address_space(1))) double gdouble;
 constexpr int kSmallJacobi = 128;
 
-// v from lane l ^ pattern of the DPP control CTRL (all 64 lanes active), FP64
+// v from the lane that the DPP control CTRL names (all 64 lanes active; the
+// patterns used here read within a row of 16 lanes, so every lane is written
+// and no old value is needed), FP64
 template <int CTRL>
 __device__ inline double dpp_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 // sum over each aligned group of 16 lanes, result in every lane of the group:
@@ -1526,6 +1528,14 @@ __device__ inline double sum16(double v)
     v += dpp_f64<0x4E>(v);
     v += dpp_f64<0x141>(v);
     v += dpp_f64<0x140>(v);
+    return v;
+}
+// the same over aligned groups of 8 lanes (the first three stages)
+__device__ inline double sum8(double v)
+{
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
     return v;
 }
 
@@ -1683,22 +1693,27 @@ __global__ __launch_bounds__(1024) void jacobi_small_kernel(JacobiBatch jobs, in
 // even and (2p+1, 2p+2) when s is odd, rotates each pair and swaps the two
 // columns' positions.  After ne steps the order is reversed and every pair has
 // met once (odd-even transposition sort of a reversed sequence), so a sweep is
-// ne steps.  Pair p is held in registers by the 16 lanes of group p of a
-// 1024-thread workgroup: lane l holds rows l, l + 16, ..., l + 112 of both
-// columns of X and of V (32 doubles), so all 16 lanes share the dot products
-// and the four waves per SIMD hide each other's latency.  Between steps each
-// pair hands one column to a neighbour through LDS: per step half of the
-// columns move and nothing else touches memory.
+// ne steps.  Pair p is held in registers by the 8 lanes of group p of a
+// 512-thread workgroup: lane l holds rows l, l + 8, ..., l + 120 of both
+// columns of X and of V (64 doubles).  Every wave computes the rotation of its
+// eight pairs once, so the per-pair scalar work (the lane sums and the
+// rotation parameters) is issued by two waves per SIMD; with 16 lanes per pair
+// it took four and set the step time.  Between steps each pair hands one
+// column to a neighbour through LDS: per step half of the columns move and
+// nothing else touches memory.
 constexpr int kRegJacobi = 128;
-constexpr int kRegThreads = 1024;
+constexpr int kRegLanes = 8;                       // lanes per column pair
+constexpr int kRegThreads = kRegJacobi / 2 * kRegLanes;
 
 template <bool WANT_V>
 __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch jobs, int max_sweeps)
 {
-    constexpr int NP = kRegJacobi / 2;             // pairs = 16-lane groups
-    constexpr int RL = kRegJacobi / 16;            // rows per lane
-    constexpr int XS = 2 * kRegJacobi + 16;        // LDS column slot: X rows, V rows, pad
-    static_assert(NP * 16 == kRegThreads, "one pair per 16-lane group");
+    constexpr int NP = kRegJacobi / 2;             // pairs = 8-lane groups
+    constexpr int RL = kRegJacobi / kRegLanes;     // rows per lane
+    // LDS column slot: X rows, V rows, and a pad that puts the groups of a
+    // wave on different banks (slot stride = 64 bytes modulo 256)
+    constexpr int XS = 2 * kRegJacobi + kRegLanes;
+    static_assert(NP * kRegLanes == kRegThreads && kRegLanes == 8, "one pair per 8-lane group");
     __shared__ __attribute__((aligned(16))) double xfer[NP][XS];
     __shared__ __attribute__((aligned(16))) double park[XS];
     __shared__ int xid[NP];
@@ -1713,14 +1728,14 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
     const int m = jb.m, n = jb.n;
     const int ne = n + (n & 1);
     const int P = ne / 2;
-    const int tid = threadIdx.x, p = tid >> 4, l16 = tid & 15;
+    const int tid = threadIdx.x, p = tid >> 3, l8 = tid & 7;
 
     // columns at positions 2p (a) and 2p+1 (b): X rows in ax/bx, V rows in av/bv
     double ax[RL], bx[RL], av[RL], bv[RL];
     int ia = 2 * p, ib = 2 * p + 1;
 #pragma unroll
     for (int u = 0; u < RL; ++u) {
-        const int r = l16 + 16 * u;
+        const int r = l8 + 8 * u;
         const bool live = p < P;
         ax[u] = (live && r < m && ia < n) ? jb.X[(int64_t)ia * m + r] : 0.0;
         bx[u] = (live && r < m && ib < n) ? jb.X[(int64_t)ib * m + r] : 0.0;
@@ -1731,8 +1746,8 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
         double t = 0.0;
 #pragma unroll
         for (int u = 0; u < RL; ++u) t += ax[u] * ax[u] + bx[u] * bx[u];
-        t = sum16(t);
-        if (l16 == 0) gsum[p] = t;
+        t = sum8(t);
+        if (l8 == 0) gsum[p] = t;
         __syncthreads();
         if (tid == 0) {
             double f = 0.0;
@@ -1760,21 +1775,34 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             be += Rx[u] * Rx[u];
             ga += Lx[u] * Rx[u];
         }
-        al = sum16(al);
-        be = sum16(be);
-        ga = sum16(ga);
+        al = sum8(al);
+        be = sum8(be);
+        ga = sum8(ga);
         if (!(p < P && (!odd || p < P - 1))) return;
         double c = 1.0, sn = 0.0;
         if (ga != 0.0 && al > noise2 && be > noise2 && ga * ga > tol2 * (al * be)) {
             // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = d / g2,
             // numerator and denominator scaled by |g2|: one division fewer
+            // (the quotient and 1 / sqrt(1 + t^2) from the hardware reciprocal
+            // and reciprocal square root, each refined by two Newton steps to
+            // full FP64 accuracy; the denominator is at least |g2| > 0 and
+            // 1 + t^2 lies in [1, 2])
             const double d = be - al, g2 = 2.0 * ga;
             const double sg = (d == 0.0 || ((d > 0.0) == (g2 > 0.0))) ? 1.0 : -1.0;
-            const double t = sg * fabs(g2) / (fabs(d) + sqrt(d * d + g2 * g2));
-            c = 1.0 / sqrt(1.0 + t * t);
+            const double den = fabs(d) + sqrt(d * d + g2 * g2);
+            double q = __builtin_amdgcn_rcp(den);
+            q = fma(q, fma(-den, q, 1.0), q);
+            q = fma(q, fma(-den, q, 1.0), q);
+            const double t = sg * fabs(g2) * q;
+            const double h = fma(t, t, 1.0);
+            double y = __builtin_amdgcn_rsq(h);
+            y = y * fma(-0.5 * h * y, y, 1.5);
+            y = y * fma(-0.5 * h * y, y, 1.5);
+            c = y;
             sn = c * t;
             my_rot = true;
-            my_max = fmaxf(my_max, (float)(ga * ga / (al * be)));
+            // only compared with kJacobiDone: the unrefined reciprocal suffices
+            my_max = fmaxf(my_max, (float)(ga * ga * __builtin_amdgcn_rcp(al * be)));
         }
 #pragma unroll
         for (int u = 0; u < RL; ++u) {
@@ -1796,17 +1824,17 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
     };
     auto put = [&](double* dst, const double (&x)[RL], const double (&v)[RL]) {
 #pragma unroll
-        for (int u = 0; u < RL; ++u) dst[l16 + 16 * u] = x[u];
+        for (int u = 0; u < RL; ++u) dst[l8 + 8 * u] = x[u];
         if (WANT_V)
 #pragma unroll
-            for (int u = 0; u < RL; ++u) dst[kRegJacobi + l16 + 16 * u] = v[u];
+            for (int u = 0; u < RL; ++u) dst[kRegJacobi + l8 + 8 * u] = v[u];
     };
     auto get = [&](const double* src, double (&x)[RL], double (&v)[RL]) {
 #pragma unroll
-        for (int u = 0; u < RL; ++u) x[u] = src[l16 + 16 * u];
+        for (int u = 0; u < RL; ++u) x[u] = src[l8 + 8 * u];
         if (WANT_V)
 #pragma unroll
-            for (int u = 0; u < RL; ++u) v[u] = src[kRegJacobi + l16 + 16 * u];
+            for (int u = 0; u < RL; ++u) v[u] = src[kRegJacobi + l8 + 8 * u];
     };
 
     // Registers a and b trade roles between the two halves of a double step:
@@ -1827,7 +1855,7 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             // even -> odd: send position 2p (a) to p-1 (p = 0: park), receive 2p+2 into a
             if (p < P) {
                 put(p == 0 ? park : xfer[p], ax, av);
-                if (l16 == 0) {
+                if (l8 == 0) {
                     if (p == 0) park_id = ia;
                     else xid[p] = ia;
                 }
@@ -1848,7 +1876,7 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             // odd -> even: send position 2p+2 (a) to p+1, receive 2p into a (p = 0: park)
             if (p + 1 < P) {
                 put(xfer[p], ax, av);
-                if (l16 == 0) xid[p] = ia;
+                if (l8 == 0) xid[p] = ia;
             }
             __syncthreads();
             if (p < P) {
@@ -1857,7 +1885,7 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             }
             __syncthreads();
         }
-        if (l16 == 0 && my_rot) {
+        if (l8 == 0 && my_rot) {
             rotated = 1;
             atomicMax(&maxr, __float_as_uint(my_max));
         }
@@ -1879,9 +1907,9 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
             na += ax[u] * ax[u];
             nb += bx[u] * bx[u];
         }
-        na = sum16(na);
-        nb = sum16(nb);
-        if (p < P && l16 == 0) {
+        na = sum8(na);
+        nb = sum8(nb);
+        if (p < P && l8 == 0) {
             if (ia >= 0 && ia < n) sig[ia] = sqrt(na);
             if (ib >= 0 && ib < n) sig[ib] = sqrt(nb);
         }
@@ -1907,11 +1935,11 @@ __global__ __launch_bounds__(kRegThreads) void jacobi_reg_kernel(JacobiBatch job
         const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
 #pragma unroll
         for (int u = 0; u < RL; ++u) {
-            const int r = l16 + 16 * u;
+            const int r = l8 + 8 * u;
             if (r < m) jb.U[(int64_t)dst * m + r] = (side == 0 ? ax[u] : bx[u]) * inv;
             if (WANT_V && r < n) jb.V[(int64_t)dst * n + r] = side == 0 ? av[u] : bv[u];
         }
-        if (l16 == 0) jb.S[dst] = sj;
+        if (l8 == 0) jb.S[dst] = sj;
     }
 }
 
