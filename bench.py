@@ -350,6 +350,15 @@ def main():
                             "tol 1e-9, max_iter %d" % (len(reqs), SERVING_MAX_ITER))
         serving["failed"] = sum(1 for r in reqs if r.status not in (0, ctm.CTM_ENOCONV))
         serving["not_converged"] = sum(1 for r in reqs if r.status == ctm.CTM_ENOCONV)
+        # where the unconverged requests sit: above the simple-cubic Ising
+        # critical coupling (0.22165) a symmetric tensor is on the ordered side
+        # and its one-site environment need not converge; by bond dimension D
+        nc = [r for r in reqs if r.status == ctm.CTM_ENOCONV]
+        serving["not_converged_split"] = {
+            "beta_above_0.22165": sum(1 for r in nc if r.beta > 0.2216544),
+            "beta_below_0.22165": sum(1 for r in nc if r.beta <= 0.2216544),
+            "requests_above_0.22165": sum(1 for r in reqs if r.beta > 0.2216544),
+            "by_D": {str(D): sum(1 for r in nc if r.D == D) for D in sorted({r.D for r in reqs})}}
         serving["failures"] = ["request %d (D=%d, chi=%d, beta=%.4f): %s" % (r.rid, r.D, r.chi, r.beta, r.error)
                                for r in reqs if r.status not in (0, ctm.CTM_ENOCONV)]
 
