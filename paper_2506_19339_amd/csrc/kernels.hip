@@ -2151,7 +2151,13 @@ __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double
             for (int t = 0; t < kCholB; ++t) {
                 if (t >= nb) break;
                 const double piv = readlane_f64(hi ? rs[t][1] : rs[t][0], el + t);
-                const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+                // reciprocal pivot: hardware reciprocal and two Newton steps
+                // (full FP64 accuracy; the serial chain of the panel is shorter
+                // than with the IEEE division sequence)
+                double q = __builtin_amdgcn_rcp(piv);
+                q = fma(q, fma(-piv, q, 1.0), q);
+                q = fma(q, fma(-piv, q, 1.0), q);
+                const double inv = piv > 0.0 ? q : 0.0;
                 if (lane == 0) binv[buf][t] = inv;
 #pragma unroll
                 for (int t2 = t + 1; t2 < kCholB; ++t2) {
@@ -2200,11 +2206,15 @@ __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double
                 for (int s = 0; s < kCholSlots; ++s) {
                     const int i = ow + kCholOwners * s;
                     if (i >= j0 + nb && i < k) {
+                        // s0 = 0 once entry 64 is passed and x1 = 0 until it
+                        // is reached: the updates run unconditionally (exact
+                        // no-ops then), which saves the selects that the
+                        // conditional form compiled to
                         const double f = bS[buf][t][i] * inv;
-                        if (s_lo) S[s][0] -= f * s0;
+                        S[s][0] -= f * s0;
                         S[s][1] -= f * s1;
                         Xr[s][0] -= f * x0;
-                        if (x_hi) Xr[s][1] -= f * x1;
+                        Xr[s][1] -= f * x1;
                     }
                 }
             }
