@@ -2066,15 +2066,18 @@ __global__ __launch_bounds__(1024) void cholqr_kernel(CholBatch jobs, double shi
 // Waves 1-15 own the rows (row i in wave 1 + i % 15, slot i / 15; each lane
 // holds the entries e = lane and lane + 64 of its rows of the Schur
 // complement S and of the elimination matrix X).  Per block of kCholB columns
-// j0 .. j0+nb-1: the owners publish the block's rows to LDS; wave 0 (the panel
-// wave) eliminates within the block in registers, broadcasting the factors
-// with readlane, and writes back the block rows as they stand at their own
-// pivot step together with the reciprocal pivots; every row below the block
-// then applies the nb eliminations S_i -= f S_t, X_i -= f X_t with
-// f = S_t[i] / p_t (S_t[i] = S_i[t] by symmetry of the Schur complement).
-// Two barriers per block instead of one per column; the block buffers are
-// double-buffered.  Entries that are zero by structure are skipped: S_i[e]
-// for e < j0 (eliminated columns) and X_t[e] for e >= j0 + nb.
+// j0 .. j0+nb-1: wave 0 (the panel wave) eliminates within the block in
+// registers, broadcasting the factors with readlane, and writes back the
+// block rows as they stand at their own pivot step together with the
+// reciprocal pivots; every row below the block then applies the nb
+// eliminations S_i -= f S_t, X_i -= f X_t with f = S_t[i] / p_t (S_t[i] =
+// S_i[t] by symmetry of the Schur complement).  Look-ahead: after a block's
+// panel step the owners first bring the next block's rows up to date and
+// publish them, so that the panel wave eliminates the next block while the
+// owners apply the current one to the remaining rows.  Every row receives
+// the blocks in order, with the same factors, as without the look-ahead.  Two
+// barriers per block instead of one per column; the block buffers are
+// double-buffered.
 constexpr int kCholReg = 128;
 constexpr int kCholB = 8;
 constexpr int kCholOwners = 15;
@@ -2085,6 +2088,39 @@ __device__ inline double readlane_f64(double v, int l)
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
+}
+
+// The eliminations of one block (pivot rows bSb / bXb [0, nbb) as they stand
+// at their own pivot steps, reciprocal pivots binvb, first column jb0)
+// applied to the owner's rows i in [lo, hi): S_i -= f S_t, X_i -= f X_t with
+// f = S_t[i] / p_t, pivots in order.  s0 = 0 once entry 64 is passed and
+// x1 = 0 until it is reached, so all four updates run unconditionally (exact
+// no-ops then; the conditional form compiled to selects).
+__device__ __forceinline__ void chol_apply_block(double (&S)[kCholSlots][2], double (&Xr)[kCholSlots][2],
+                                                 const double (&bSb)[kCholB][kCholReg],
+                                                 const double (&bXb)[kCholB][kCholReg], const double* binvb,
+                                                 int jb0, int nbb, int ow, int lane, int lo, int hi)
+{
+    const bool s_lo = jb0 < 64;                   // S entries 0-63 still live
+    const bool x_hi = jb0 + nbb > 64;             // X_t entries 64-127 can be nonzero
+#pragma unroll
+    for (int t = 0; t < kCholB; ++t) {
+        if (t >= nbb) break;
+        const double s0 = s_lo ? bSb[t][lane] : 0.0, s1 = bSb[t][lane + 64];
+        const double x0 = bXb[t][lane], x1 = x_hi ? bXb[t][lane + 64] : 0.0;
+        const double inv = binvb[t];
+#pragma unroll
+        for (int s = 0; s < kCholSlots; ++s) {
+            const int i = ow + kCholOwners * s;
+            if (i >= lo && i < hi) {
+                const double f = bSb[t][i] * inv;
+                S[s][0] -= f * s0;
+                S[s][1] -= f * s1;
+                Xr[s][0] -= f * x0;
+                Xr[s][1] -= f * x1;
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double shift)
@@ -2114,24 +2150,25 @@ __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double
             Xr[s][u] = (ok && i == e) ? 1.0 : 0.0;
         }
     }
-    int buf = 0;
-    for (int j0 = 0; j0 < k; j0 += kCholB, buf ^= 1) {
-        const int nb = min(kCholB, k - j0);
-        // the owners publish the block's rows (eliminated by all earlier blocks)
-        if (ow >= 0) {
+    // the owners publish the rows of the first block
+    if (ow >= 0) {
 #pragma unroll
-            for (int s = 0; s < kCholSlots; ++s) {
-                const int i = ow + kCholOwners * s;
-                if (i >= j0 && i < j0 + nb) {
+        for (int s = 0; s < kCholSlots; ++s) {
+            const int i = ow + kCholOwners * s;
+            if (i < min(kCholB, k)) {
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        bS[buf][i - j0][lane + 64 * u] = S[s][u];
-                        bX[buf][i - j0][lane + 64 * u] = Xr[s][u];
-                    }
+                for (int u = 0; u < 2; ++u) {
+                    bS[0][i][lane + 64 * u] = S[s][u];
+                    bX[0][i][lane + 64 * u] = Xr[s][u];
                 }
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int j0 = 0; j0 < k; j0 += kCholB, buf ^= 1) {
+        const int nb = min(kCholB, k - j0);
+        const int j1 = j0 + nb, nb1 = min(kCholB, k - j1);   // the next block (nb1 <= 0: none)
         if (ow < 0) {
             // panel wave: elimination within the block, in the registers that
             // hold rows in the owner waves (the panel wave owns none)
@@ -2178,6 +2215,11 @@ __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double
                         bS[buf][t][lane + 64 * u] = rs[t][u];
                         bX[buf][t][lane + 64 * u] = rx[t][u];
                     }
+        } else if (j0 > 0) {
+            // look-ahead: while the panel wave works on this block, the
+            // previous block's eliminations reach the rows below this block
+            // (the rows of this block took them before it was published)
+            chol_apply_block(S, Xr, bS[buf ^ 1], bX[buf ^ 1], binv[buf ^ 1], j0 - kCholB, kCholB, ow, lane, j1, k);
         }
         __syncthreads();
         if (ow >= 0) {
@@ -2185,7 +2227,7 @@ __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double
 #pragma unroll
             for (int s = 0; s < kCholSlots; ++s) {
                 const int i = ow + kCholOwners * s;
-                if (i >= j0 && i < j0 + nb) {
+                if (i >= j0 && i < j1) {
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
                         S[s][u] = bS[buf][i - j0][lane + 64 * u];
@@ -2193,32 +2235,25 @@ __global__ __launch_bounds__(1024) void cholqr_reg_kernel(CholBatch jobs, double
                     }
                 }
             }
-            // rows below the block: nb eliminations each
-            const bool s_lo = j0 < 64;                // S entries 0-63 still live
-            const bool x_hi = j0 + nb > 64;           // X_t entries 64-127 can be nonzero
-#pragma unroll
-            for (int t = 0; t < kCholB; ++t) {
-                if (t >= nb) break;
-                const double s0 = s_lo ? bS[buf][t][lane] : 0.0, s1 = bS[buf][t][lane + 64];
-                const double x0 = bX[buf][t][lane], x1 = x_hi ? bX[buf][t][lane + 64] : 0.0;
-                const double inv = binv[buf][t];
+            // the next block's rows (at most one per owner: 8 consecutive
+            // rows fall on 8 different owners) take this block's
+            // eliminations first and are published for the panel wave
+            if (nb1 > 0) {
+                chol_apply_block(S, Xr, bS[buf], bX[buf], binv[buf], j0, nb, ow, lane, j1, j1 + nb1);
 #pragma unroll
                 for (int s = 0; s < kCholSlots; ++s) {
                     const int i = ow + kCholOwners * s;
-                    if (i >= j0 + nb && i < k) {
-                        // s0 = 0 once entry 64 is passed and x1 = 0 until it
-                        // is reached: the updates run unconditionally (exact
-                        // no-ops then), which saves the selects that the
-                        // conditional form compiled to
-                        const double f = bS[buf][t][i] * inv;
-                        S[s][0] -= f * s0;
-                        S[s][1] -= f * s1;
-                        Xr[s][0] -= f * x0;
-                        Xr[s][1] -= f * x1;
+                    if (i >= j1 && i < j1 + nb1) {
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            bS[buf ^ 1][i - j1][lane + 64 * u] = S[s][u];
+                            bX[buf ^ 1][i - j1][lane + 64 * u] = Xr[s][u];
+                        }
                     }
                 }
             }
         }
+        __syncthreads();
     }
     // pivots p_i = S_ii; T[i][c] = p_i^-1/2 X_ic d_c
     if (ow < 0) return;
