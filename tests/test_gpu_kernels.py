@@ -214,8 +214,8 @@ def test_gemm_reduced_precision(lib, prec, ta, tb, M, N, K, batch, cap):
     assert np.max(np.abs(C - exact) / (np.abs(exact).max() + 1e-300)) <= 4 * u * np.sqrt(K) + 1e-6 * (prec == 1)
 
 
-@pytest.mark.parametrize("k,rank", [(1, 1), (16, 16), (100, 100), (128, 128), (128, 90), (135, 135), (135, 90),
-                                    (141, 141), (160, 160)])
+@pytest.mark.parametrize("k,rank", [(1, 1), (9, 9), (16, 16), (63, 63), (65, 65), (100, 100), (127, 127),
+                                    (128, 128), (128, 90), (135, 135), (135, 90), (141, 141), (160, 160)])
 def test_cholqr_factor(lib, k, rank):
     """T = L^-1 D with L L^T = D G D + shift I, T lower triangular (k <= 128:
     register-resident kernel; 135, 141: LDS; 160: global memory).  Full rank: T matches LAPACK's factor.
@@ -252,8 +252,8 @@ def test_cholqr_factor(lib, k, rank):
         assert np.max(np.abs(Q2 @ Q2.T - np.eye(k))) <= 1e-9
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (8, 8), (33, 17), (64, 64), (100, 100), (128, 128), (128, 117),
-                                 (129, 128), (300, 120), (256, 256)])
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 2), (3, 3), (8, 8), (33, 17), (64, 64), (65, 65), (100, 100),
+                                 (127, 127), (128, 3), (128, 128), (128, 117), (129, 128), (300, 120), (256, 256)])
 def test_jacobi_svd_matches_numpy(lib, m, n):
     rng = np.random.default_rng(m + 100 * n)
     X = rng.standard_normal((m, n))
