@@ -279,6 +279,31 @@ def test_jacobi_svd_matches_numpy(lib, m, n):
     assert np.allclose(V.T @ V, np.eye(n), atol=1e-13)
 
 
+@pytest.mark.parametrize("n,off,max_sweeps", [(128, 0.0, 1), (128, 1e-6, 3), (100, 1e-6, 3), (117, 1e-6, 3)])
+def test_jacobi_stops_early_on_nearly_diagonal_input(lib, n, off, max_sweeps):
+    """The warm Rayleigh-Ritz cores are nearly diagonal.  One-sided Jacobi
+    converges quadratically there, and the kernel stops after the first sweep
+    whose rotations all had cos^2 < 1e-16 (or that rotated nothing): a
+    diagonal input takes one sweep, off-diagonal entries of relative size 1e-6
+    at most three; the factorisation still matches numpy."""
+    rng = np.random.default_rng(n)
+    d = np.logspace(0, -8, n) * rng.choice([-1.0, 1.0], n)
+    # off-diagonal entries scaled by the smaller of the two diagonal
+    # magnitudes: every pair of columns starts with |cos| ~ 2 off
+    X = np.diag(d) + off * rng.standard_normal((n, n)) * np.minimum.outer(np.abs(d), np.abs(d))
+    U = np.zeros((n, n))
+    V = np.zeros((n, n))
+    S = np.zeros(n)
+    sweeps = ctypes.c_int(0)
+    assert lib.ctm_selftest_jacobi(n, n, _p(np.asfortranarray(X).ravel(order="F").copy()), _p(U), _p(S), _p(V),
+                                   ctypes.byref(sweeps)) == 0
+    assert 1 <= sweeps.value <= max_sweeps, sweeps.value
+    s_ref = np.linalg.svd(X, compute_uv=False)
+    assert np.max(np.abs(S - s_ref)) <= 1e-15 * n * s_ref[0]
+    assert np.allclose((U.T * S) @ V, X, atol=1e-14)
+    assert np.allclose(V @ V.T, np.eye(n), atol=1e-13)
+
+
 @pytest.mark.parametrize("rows,m,n", [(1, 1, 1), (100, 5000, 1000), (300, 257, 3), (64, 64, 64)])
 def test_sign_fix_flips_whole_rows(lib, rows, m, n):
     """Each row pair (u_i, v_i) is negated as a whole exactly when the entry of
