@@ -75,6 +75,45 @@ def gpu_eval(ctm, torch, w, A, g, stream, profile=False, precision=0, refine=Fal
     return c, dict(iters=done, delta=delta, converged=conv, f=f)
 
 
+def factor_kernels():
+    """The kernels of a move timed alone through the self-test library (the
+    register Cholesky-QR factor and one-sided Jacobi on three 128-wide
+    problems per launch, as in a projector stage; the FP64 GEMM at the most
+    frequent product shapes of a D = 5, chi = 100 evaluation, with and
+    without the split-K plan)."""
+    import ctypes
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2506_19339_amd", "libctm_selftest.so")
+    if not os.path.exists(path):
+        raise SystemExit("libctm_selftest.so is not built")
+    lib = ctypes.CDLL(path)
+    us = ctypes.c_double(0.0)
+
+    def timed(fn, *a):
+        rc = fn(*a, ctypes.byref(us))
+        if rc != 0:
+            raise SystemExit("self-test timing call failed (%d)" % rc)
+        return us.value
+
+    f = lib.ctm_selftest_time_factor
+    for which, name in ((0, "cholqr_reg_kernel"), (1, "jacobi_reg_kernel with V"), (2, "jacobi_reg_kernel without V")):
+        sweeps = 5 if which else 0
+        t = timed(f, which, 128, 3, sweeps, 50 if which == 0 else 10)
+        row = {"kernel": name, "k": 128, "problems_per_launch": 3, "us_per_launch": round(t, 1)}
+        if which:
+            row.update(sweeps=sweeps, us_per_sweep=round(t / sweeps, 1))
+        print(json.dumps(row), flush=True)
+    g = lib.ctm_selftest_time_gemm
+    for M, N, K in ((4000, 2500, 1000), (1000, 1000, 1000), (10000, 500, 1000), (20000, 500, 500),
+                    (1000, 2500, 1000), (2500, 500, 1000), (50000, 200, 100), (10000, 100, 1000),
+                    (1000, 100, 1000), (500, 100, 10000)):
+        t1 = timed(g, M, N, K, 1, 20)
+        t0 = timed(g, M, N, K, 0, 20)
+        fl = 2.0 * M * N * K
+        print(json.dumps({"kernel": "gemm_f64", "M": M, "N": N, "K": K,
+                          "us_split_plan": round(t1, 1), "tflops_split_plan": round(fl / t1 / 1e6, 1),
+                          "us_no_split": round(t0, 1), "tflops_no_split": round(fl / t0 / 1e6, 1)}), flush=True)
+
+
 def method_sweep(ctm, torch, steps, moves=20, skip=5):
     """Split-CTMRG against the reduced method on the same kernels (the runtime
     comparison of Sec. IV A): time per move of both networks for D = 2..6 at
@@ -147,6 +186,9 @@ def main():
     ap.add_argument("--method-sweep", action="store_true",
                     help="only compare split-CTMRG with the reduced method: time per move for "
                          "D = 2..6 at chi = D^2 and chi = 100 (one JSON line per case)")
+    ap.add_argument("--factor-kernels", action="store_true",
+                    help="only time the factorisation kernels and the FP64 GEMM alone at the "
+                         "shapes of a D = 5, chi = 100 move (one JSON line per case)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -170,6 +212,9 @@ def main():
 
     if args.method_sweep:
         method_sweep(ctm, torch, args.steps)
+        return
+    if args.factor_kernels:
+        factor_kernels()
         return
     if args.reduced_only:
         w = WORKLOADS[args.workload]

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdint>
 #include <vector>
 
 #include "kernels.h"
@@ -293,6 +295,135 @@ int ctm_selftest_jacobi(int m, int n, const double* X, double* U, double* S, dou
     (void)hipFree(dU);
     (void)hipFree(dV);
     (void)hipFree(dS);
+    return rc;
+}
+
+// Timing of the factorisation kernels alone (device buffers, the same launch
+// shapes as in a move): which = 0, the register Cholesky-QR factor of nprob
+// k x k Gram matrices (k <= 128); which = 1 and 2, the register one-sided
+// Jacobi of nprob k x k matrices with and without V, stopped after exactly
+// `sweeps` sweeps (random input does not converge earlier).  *us receives the
+// average time per launch over `reps` launches after a few untimed ones.
+int ctm_selftest_time_factor(int which, int k, int nprob, int sweeps, int reps, double* us)
+{
+    if (k < 1 || k > 128 || nprob < 1 || nprob > ctmk::kMaxJacobiBatch || reps < 1 || !us) return 2;
+    std::vector<double> h((size_t)k * k);
+    uint64_t z = 0x9e3779b97f4a7c15ull;
+    auto uni = [&]() {   // splitmix64 -> [-1, 1)
+        z += 0x9e3779b97f4a7c15ull;
+        uint64_t x = z;
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        x ^= x >> 31;
+        return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    };
+    if (which == 0) {
+        // Gram matrix of k graded random rows of length 4k
+        std::vector<double> y((size_t)k * 4 * k);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < 4 * k; ++j) y[(size_t)i * 4 * k + j] = uni() * std::pow(10.0, -6.0 * i / k);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double v = 0.0;
+                for (int t = 0; t < 4 * k; ++t) v += y[(size_t)i * 4 * k + t] * y[(size_t)j * 4 * k + t];
+                h[(size_t)i * k + j] = h[(size_t)j * k + i] = v;
+            }
+    } else {
+        for (double& v : h) v = uni();
+    }
+    std::vector<double*> bufs;
+    auto dev = [&](size_t n) {
+        double* d = dev_copy<double>(nullptr, n);
+        bufs.push_back(d);
+        return d;
+    };
+    int rc = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 1;
+    const size_t kk = (size_t)k * k;
+    if (which == 0) {
+        ctmk::CholBatch cb{};
+        cb.n = nprob;
+        for (int j = 0; j < nprob; ++j) {
+            double *G = dev(kk), *w = dev(2 * (size_t)k), *T = dev(kk);
+            if (!G || !w || !T || hipMemcpy(G, h.data(), kk * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = 1;
+            cb.job[j] = ctmk::CholJob{G, w, T, k};
+        }
+        if (!rc) {
+            for (int r = 0; r < 3; ++r) ctmk::cholqr(nullptr, cb, 1e-14);
+            rc |= hipDeviceSynchronize() != hipSuccess;
+            rc |= hipEventRecord(e0, nullptr) != hipSuccess;
+            for (int r = 0; r < reps; ++r) ctmk::cholqr(nullptr, cb, 1e-14);
+            rc |= hipEventRecord(e1, nullptr) != hipSuccess;
+        }
+    } else {
+        ctmk::JacobiBatch jb{};
+        jb.n = nprob;
+        for (int j = 0; j < nprob; ++j) {
+            double *X = dev(kk), *W = dev(kk), *U = dev(kk), *V = dev(kk), *S = dev((size_t)k);
+            if (!X || !W || !U || !V || !S || hipMemcpy(X, h.data(), kk * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                rc = 1;
+            jb.job[j] = ctmk::JacobiJob{X, W, U, V, S, k, k, which == 1 ? 1 : 0, nullptr};
+        }
+        if (!rc && !ctmk::jacobi_reads_only(jb)) rc = 2;   // the register kernel reads X only
+        if (!rc) {
+            ctmk::jacobi_svd(nullptr, jb, sweeps);
+            rc |= hipDeviceSynchronize() != hipSuccess;
+            rc |= hipEventRecord(e0, nullptr) != hipSuccess;
+            for (int r = 0; r < reps; ++r) ctmk::jacobi_svd(nullptr, jb, sweeps);
+            rc |= hipEventRecord(e1, nullptr) != hipSuccess;
+        }
+    }
+    float ms = 0.0f;
+    if (!rc) {
+        rc |= hipEventSynchronize(e1) != hipSuccess;
+        rc |= hipEventElapsedTime(&ms, e0, e1) != hipSuccess;
+        *us = 1000.0 * ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (double* d : bufs) (void)hipFree(d);
+    return rc;
+}
+
+// Time per launch of the FP64 GEMM C = A B (row-major, M x K times K x N,
+// zero operands) with the split-K plan of the library (split = 1: a 32 MiB
+// workspace as in a move) or without split-K (split = 0).
+int ctm_selftest_time_gemm(int M, int N, int K, int split, int reps, double* us)
+{
+    if (M < 1 || N < 1 || K < 1 || reps < 1 || !us) return 2;
+    const int64_t ws_cap = (int64_t)1 << 22;
+    double *A = dev_copy<double>(nullptr, (size_t)M * K), *B = dev_copy<double>(nullptr, (size_t)K * N);
+    double *C = dev_copy<double>(nullptr, (size_t)M * N), *W = split ? dev_copy<double>(nullptr, (size_t)ws_cap) : nullptr;
+    int rc = (!A || !B || !C || (split && !W)) ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc) {
+        rc |= hipMemset(A, 0, (size_t)M * K * sizeof(double)) != hipSuccess;
+        rc |= hipMemset(B, 0, (size_t)K * N * sizeof(double)) != hipSuccess;
+        rc |= hipEventCreate(&e0) != hipSuccess;
+        rc |= hipEventCreate(&e1) != hipSuccess;
+    }
+    if (!rc) {
+        auto run = [&]() {
+            ctmk::gemm_f64(nullptr, false, false, M, N, K, 1.0, A, K, 0, B, N, 0, 0.0, C, N, 0, 1, W,
+                           split ? ws_cap : 0, nullptr);
+        };
+        for (int r = 0; r < 3; ++r) run();
+        rc |= hipDeviceSynchronize() != hipSuccess;
+        rc |= hipEventRecord(e0, nullptr) != hipSuccess;
+        for (int r = 0; r < reps; ++r) run();
+        rc |= hipEventRecord(e1, nullptr) != hipSuccess;
+        float ms = 0.0f;
+        rc |= hipEventSynchronize(e1) != hipSuccess;
+        rc |= hipEventElapsedTime(&ms, e0, e1) != hipSuccess;
+        if (!rc) *us = 1000.0 * ms / reps;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(A);
+    (void)hipFree(B);
+    (void)hipFree(C);
+    if (W) (void)hipFree(W);
     return rc;
 }
 
