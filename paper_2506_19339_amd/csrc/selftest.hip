@@ -339,7 +339,10 @@ int ctm_selftest_time_factor(int which, int k, int nprob, int sweeps, int reps, 
     };
     int rc = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return 1;
+    }
     const size_t kk = (size_t)k * k;
     if (which == 0) {
         ctmk::CholBatch cb{};
