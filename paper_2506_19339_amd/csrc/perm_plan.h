@@ -20,6 +20,7 @@ namespace ctmk {
 constexpr int kPermTileElems = 2048;   // doubles per tile (16 KiB of LDS)
 constexpr int kPermTileSide = 256;     // largest chunk of either block
 constexpr int kPermBlockDims = 4;
+constexpr int64_t kPermShortRunElems = 1250000;   // size from which 4-element block runs are tiled
 constexpr int kPermRestDims = 12;
 
 // q = x / d for x < 2^31 as (umulhi(x, mul) + x) >> shr, with shr =
@@ -117,7 +118,12 @@ inline bool plan_perm_tile(int rank, const int64_t* od, const int64_t* is, PermT
         Lout *= v[k].d;
     }
     grow_in();
-    if (t.nin == 0 || t.nout == 0 || Lin * U < 8 || Lout * U < 8) return false;
+    // shortest block run (elements) worth a tile: 8, and 4 for large permutes,
+    // where a tile with 4-7 element rows (partial writes or reads of 32-56
+    // bytes) still beats the element-wise kernel's strided reads (measured
+    // from 1.25e6 elements up; below that the element-wise kernel is faster)
+    const int64_t min_run = os >= kPermShortRunElems ? 4 : 8;
+    if (t.nin == 0 || t.nout == 0 || Lin * U < min_run || Lout * U < min_run) return false;
     t.nrest = 0;
     int64_t rest = 1;
     for (int k = 0; k < r; ++k) {

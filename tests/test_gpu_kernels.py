@@ -130,7 +130,8 @@ TRACED_PERMUTES = [
     ("vadpqurkl", "vdqurkapl", (5, 5, 100, 2, 2, 1, 1, 100, 5), 1),
     ("vdqurkzs", "vqurkzsd", (5, 100, 2, 2, 2, 100, 5, 5), 1),
     ("ibfprnmj", "bfrnjipm", (2, 5, 100, 2, 5, 5, 2, 100), 1),
-    ("fblnhqmt", "fblqmhtn", (100, 5, 5, 5, 100, 2, 2, 2), 0),   # output runs of 5: element-wise
+    ("fblnhqmt", "fblqmhtn", (100, 5, 5, 5, 100, 2, 2, 2), 1),   # output runs of 5, 1e7 elements: tiled
+    ("fblnhqmt", "fblqmhtn", (10, 5, 5, 5, 10, 2, 2, 2), 0),     # the same below 1.25e6 elements: element-wise
     ("sonbpmd", "nmdpbos", (5, 2, 100, 100, 2, 5, 5), 1),
 ]
 

@@ -34,7 +34,8 @@ def tiled(lib, dims, axes):
     ((3, 1000), (0, 1), 0),
     ((8, 64, 64), (1, 0, 2), 0),                     # unit of 64 contiguous in both: element-wise
     ((2, 3), (1, 0), 0),                             # too short for a tile
-    ((100, 5, 5, 5, 100, 2, 2, 2), (0, 1, 2, 5, 6, 4, 7, 3), 0),   # output runs of 5
+    ((100, 5, 5, 5, 100, 2, 2, 2), (0, 1, 2, 5, 6, 4, 7, 3), 1),   # output runs of 5, 1e7 elements
+    ((10, 5, 5, 5, 10, 2, 2, 2), (0, 1, 2, 5, 6, 4, 7, 3), 0),     # the same below 1.25e6 elements
     ((7,), (0,), 0),
 ])
 def test_plan_choice(lib, dims, axes, want):
