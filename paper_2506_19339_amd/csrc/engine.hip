@@ -648,23 +648,36 @@ struct Worker {
             else b[j].n = std::max(b[j].n, t->n());
         }
         std::sort(b, b + nb, [](const Buf& x, const Buf& y) { return x.key < y.key; });
+        // all bounces up in one launch (the copies land above everything live)
+        static_assert(ctmk::kMaxCopyBatch >= 8, "one copy batch per settle");
+        ctmk::CopyBatch up{};
         for (int j = 0; j < nb; ++j) {
             b[j].up = ws.alloc(b[j].n);
-            ctmk::copy(st, b[j].src, b[j].up, b[j].n);
+            up.src[up.cnt] = b[j].src;
+            up.dst[up.cnt] = b[j].up;
+            up.n[up.cnt++] = b[j].n;
         }
+        ctmk::copy_batch(st, up);
         const Arena::Mark above = ws.mark();
         ws.release(m);
+        // ... and all copies down in one launch, provided no final place
+        // overlaps a bounce (else the bounces stay where they are)
         bool ok = true;
+        ctmk::CopyBatch down{};
         for (int j = 0; j < nb && ok; ++j) {
             double* q = ws.alloc(b[j].n);
             for (int i = 0; i < nb; ++i)
                 if (q < b[i].up + b[i].n && b[i].up < q + b[j].n) ok = false;
             if (ok) {
-                ctmk::copy(st, b[j].up, q, b[j].n);
+                down.src[down.cnt] = b[j].up;
+                down.dst[down.cnt] = q;
+                down.n[down.cnt++] = b[j].n;
                 b[j].q = q;
             }
         }
-        if (!ok) {
+        if (ok) {
+            ctmk::copy_batch(st, down);
+        } else {
             ws.release(above);
             for (int j = 0; j < nb; ++j) b[j].q = b[j].up;
         }

@@ -73,6 +73,16 @@ void dot(hipStream_t s, const double* x, const double* y, int64_t n, double* out
 void scale_inv(hipStream_t s, double* x, int64_t n, const double* dev_scalar);
 void fill(hipStream_t s, double* x, int64_t n, double v);
 void copy(hipStream_t s, const double* a, double* b, int64_t n);
+// up to kMaxCopyBatch copies in one launch; no destination may overlap any
+// source or other destination of the batch
+constexpr int kMaxCopyBatch = 8;
+struct CopyBatch {
+    const double* src[kMaxCopyBatch];
+    double* dst[kMaxCopyBatch];
+    int64_t n[kMaxCopyBatch];
+    int cnt;
+};
+void copy_batch(hipStream_t s, const CopyBatch& cb);
 void eye(hipStream_t s, double* x, int n);
 void symmetrize(hipStream_t s, double* x, int n);
 void scale_lines(hipStream_t s, double* x, int R, int C, const double* f, int mode);

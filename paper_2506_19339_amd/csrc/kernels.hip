@@ -901,6 +901,27 @@ void copy(hipStream_t s, const double* a, double* b, int64_t n)
     hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, b, n);
 }
 
+// copy j of the batch is served by the blocks with blockIdx.y == j
+__global__ void copy_batch_kernel(CopyBatch cb)
+{
+    const int j = blockIdx.y;
+    if (j >= cb.cnt) return;
+    const double* __restrict__ a = cb.src[j];
+    double* __restrict__ b = cb.dst[j];
+    const int64_t n = cb.n[j];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+void copy_batch(hipStream_t s, const CopyBatch& cb)
+{
+    int64_t mx = 0;
+    for (int j = 0; j < cb.cnt; ++j) mx = std::max(mx, cb.n[j]);
+    if (cb.cnt <= 0 || mx <= 0) return;
+    hipLaunchKernelGGL(copy_batch_kernel, dim3(grid_for(mx), cb.cnt), dim3(256), 0, s, cb);
+}
+
 __global__ void eye_kernel(double* x, int n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n * n;
